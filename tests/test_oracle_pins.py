@@ -1,0 +1,292 @@
+"""Pins for the oracle: values the paper prints, closed forms, brute force.
+
+Each test checks the oracle against something other than itself, chosen so
+that a dropped term, a wrong sign or index, or a transposed operand in the
+oracle fails at least one of them.
+"""
+import math
+import random
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from conftest import load_golden_matrices
+from oracle import algorithms, classical, recursive, tensor
+
+ALGS = ["strassen_222_7", "fmm_333_23", "fmm_323_15", "fmm_423_20", "fmm_424_26"]
+
+
+# --- the matrix-multiplication tensor (Section 2.2) ------------------------
+
+@pytest.mark.parametrize("dims", [(2, 2, 2), (3, 2, 3), (4, 2, 3), (2, 3, 4), (3, 3, 3), (1, 4, 2)])
+def test_tensor_applied_to_vec_is_the_product(dims):
+    """T x1 vec(A) x2 vec(B) == vec(A B) for the membership rule, checked
+    against the schoolbook product on random integer matrices."""
+    M, K, N = dims
+    T = tensor.matmul_tensor(M, K, N)
+    assert len(T) == M * K * N  # MKN non-zeros
+    rng = random.Random(1)
+    for _ in range(5):
+        A = [[rng.randint(-9, 9) for _ in range(K)] for _ in range(M)]
+        B = [[rng.randint(-9, 9) for _ in range(N)] for _ in range(K)]
+        C = [[sum(A[a][b] * B[b][c] for b in range(K)) for c in range(N)] for a in range(M)]
+        z = tensor.apply_tensor(T, [x for row in A for x in row], [y for row in B for y in row], M * N)
+        assert z == [x for row in C for x in row]
+
+
+def test_tensor_222_matches_printed_slices():
+    slices = load_golden_matrices("tensor_222_slices.txt")
+    T = tensor.matmul_tensor(2, 2, 2)
+    for k, S in enumerate(slices):
+        for i in range(4):
+            for j in range(4):
+                assert T.get((i, j, k), 0) == S[i][j]
+
+
+# --- Strassen and the printed factor matrices (Sections 2.1, 2.2) ----------
+
+def test_strassen_formulas_pass_brent():
+    a = algorithms.strassen()
+    assert tensor.brent_residual(a.U, a.V, a.W, 2, 2, 2) == []
+
+
+def test_printed_uv_match_formulas_and_printed_w_is_the_erratum():
+    U, V, W = load_golden_matrices("strassen_printed_uvw.txt")
+    a = algorithms.strassen()
+    assert [list(r) for r in a.U] == U
+    assert [list(r) for r in a.V] == V
+    # The printed W fails the Brent equations (14 entries) ...
+    assert len(tensor.brent_residual(a.U, a.V, W, 2, 2, 2)) == 14
+    # ... and differs from the formulas' W by swapping the C12/C21 rows and
+    # moving C22's M6 term to M4.
+    fixed = [W[0], W[2], W[1], list(W[3])]
+    fixed[3][3], fixed[3][5] = 0, 1
+    assert [list(r) for r in a.W] == fixed
+
+
+def test_strassen_18_additions():
+    assert algorithms.additions(algorithms.strassen()) == 18
+    assert algorithms.additions(algorithms.classical_222()) == 4
+
+
+# --- the base cases (Table 2) -----------------------------------------------
+
+def _table2():
+    rows = load_golden_matrices("table2_algorithms.txt")[0]
+    return {(r[0], r[1], r[2]): r for r in rows}
+
+
+@pytest.mark.parametrize("name", ALGS + ["classical_222_8"])
+def test_tables_pass_brent(name):
+    a = algorithms.get(name)
+    assert tensor.brent_residual(a.U, a.V, a.W, a.M, a.K, a.N) == []
+
+
+@pytest.mark.parametrize("name", ALGS)
+def test_rank_matches_table2(name):
+    """The rank R equals Table 2's entry for the base case or one of its
+    permutations (<3,2,3> and <4,2,x> are permutations of the printed
+    <2,3,3>, <2,3,4>, <2,4,4>), and the printed speedup per step is
+    MKN/R - 1 rounded to a percent."""
+    a = algorithms.get(name)
+    t2 = _table2()
+    key = tuple(sorted(a.dims))
+    hits = [r for d, r in t2.items() if tuple(sorted(d)) == key and r[3] == a.R]
+    assert hits, (name, a.dims, a.R)
+    mkn = a.M * a.K * a.N
+    assert round(100 * (mkn / a.R - 1)) == hits[0][5]
+
+
+def test_table2_speedups_are_mkn_over_r():
+    for (M, K, N), r in _table2().items():
+        assert round(100 * (M * K * N / r[3] - 1)) == r[5]
+        if (M, K, N) != (3, 3, 3):
+            assert r[4] == M * K * N
+    assert _table2()[(3, 3, 3)][4] == 26  # printed; MKN is 27 (erratum)
+
+
+@pytest.mark.parametrize("name", ALGS)
+def test_propositions_21_22_give_algorithms(name):
+    a = algorithms.get(name)
+    for prop in (tensor.prop21, tensor.prop22):
+        U, V, W, (M, K, N) = prop(a.U, a.V, a.W, a.M, a.K, a.N)
+        assert tensor.brent_residual(U, V, W, M, K, N) == []
+    # composing both reaches all six permutations
+    seen = set()
+    frontier = [(a.U, a.V, a.W, a.dims)]
+    while frontier:
+        U, V, W, d = frontier.pop()
+        if d in seen:
+            continue
+        seen.add(d)
+        for prop in (tensor.prop21, tensor.prop22):
+            U2, V2, W2, d2 = prop(U, V, W, *d)
+            frontier.append((U2, V2, W2, d2))
+    assert len(seen) == len(set(__import__("itertools").permutations(a.dims)))
+
+
+@pytest.mark.parametrize("name", ALGS)
+def test_brent_catches_planted_mistakes(name):
+    """A wrong sign, a dropped term or a moved index in any factor matrix
+    must fail the Brent check."""
+    a = algorithms.get(name)
+    rng = random.Random(7)
+    for which in range(3):
+        for _ in range(3):
+            mats = [[list(r) for r in X] for X in (a.U, a.V, a.W)]
+            X = mats[which]
+            i = rng.randrange(len(X))
+            r = rng.randrange(a.R)
+            X[i][r] = -X[i][r] if X[i][r] else 1
+            assert tensor.brent_residual(*mats, a.M, a.K, a.N) != []
+
+
+# --- O1, the classical product ---------------------------------------------
+
+def test_classical_exact_on_rationals():
+    rng = random.Random(3)
+    for (m, k, n) in [(1, 1, 1), (3, 5, 2), (7, 4, 9), (16, 16, 16)]:
+        A = [[Fraction(rng.randint(-64, 64), 8) for _ in range(k)] for _ in range(m)]
+        B = [[Fraction(rng.randint(-64, 64), 4) for _ in range(n)] for _ in range(k)]
+        exact = classical.gemm_exact(A, B)
+        C = classical.gemm(np.array(A, dtype=float), np.array(B, dtype=float))
+        assert [[Fraction(x) for x in row] for row in C.tolist()] == exact
+
+
+def test_classical_within_rounding_bound():
+    """|C - AB| <= gamma_k |A||B| elementwise (Higham, Accuracy and Stability,
+    Section 3.5), against the exact rational product."""
+    rng = np.random.default_rng(5)
+    m, k, n = 6, 300, 5
+    A = rng.uniform(-1, 1, (m, k))
+    B = rng.uniform(-1, 1, (k, n))
+    C = classical.gemm(A, B)
+    u = 2.0 ** -53
+    gamma = k * u / (1 - k * u)
+    Af = [[Fraction(x) for x in row] for row in A.tolist()]
+    Bf = [[Fraction(x) for x in row] for row in B.tolist()]
+    exact = classical.gemm_exact(Af, Bf)
+    absprod = np.abs(A) @ np.abs(B)
+    for i in range(m):
+        for j in range(n):
+            assert abs(Fraction(C[i, j]) - exact[i][j]) <= Fraction(gamma * absprod[i, j])
+    Cd = classical.gemm_rows(A, B, list(range(m)), compensated=True)
+    for i in range(m):
+        for j in range(n):
+            # Dot2: error <= u|s| + gamma_k^2 sum|ab|
+            bound = u * abs(float(exact[i][j])) + gamma * gamma * absprod[i, j]
+            assert abs(Fraction(Cd[i, j]) - exact[i][j]) <= Fraction(bound) * 2
+
+
+def test_classical_not_transposed_and_rows():
+    rng = np.random.default_rng(0)
+    A = rng.integers(-8, 9, (5, 7)).astype(float)
+    B = rng.integers(-8, 9, (7, 3)).astype(float)
+    C = classical.gemm(A, B)
+    assert np.array_equal(C, A @ B)  # integer-valued: every rounding is exact
+    rows = [4, 0, 2]
+    assert np.array_equal(classical.gemm_rows(A, B, rows), C[rows])
+    assert classical.gemm(np.zeros((0, 3)), np.zeros((3, 4))).shape == (0, 4)
+    assert np.array_equal(classical.gemm(np.ones((2, 0)), np.ones((0, 3))), np.zeros((2, 3)))
+
+
+# --- O2, the recursive algorithm ---------------------------------------------
+
+def _frac_matrix(rng, r, c):
+    return np.array([[Fraction(rng.randint(-20, 20), rng.choice([1, 2, 4])) for _ in range(c)]
+                     for _ in range(r)], dtype=object)
+
+
+@pytest.mark.parametrize("name", ALGS)
+@pytest.mark.parametrize("peel", ["dynamic", "static"])
+def test_recursive_exact_on_rationals(name, peel):
+    """O2 == brute-force product exactly, sizes M^L t + r (ragged included)."""
+    a = algorithms.get(name)
+    rng = random.Random(11)
+    for L in (1, 2):
+        fm, fk, fn = a.M ** L, a.K ** L, a.N ** L
+        for (tm, tk, tn, rm, rk, rn) in [(1, 1, 1, 0, 0, 0), (1, 1, 1, 1, 1, 1),
+                                         (2, 1, 1, fm - 1, 0, 1)]:
+            m, k, n = fm * tm + rm, fk * tk + rk, fn * tn + rn
+            if m * k * n > 40000:
+                continue
+            A = _frac_matrix(rng, m, k)
+            B = _frac_matrix(rng, k, n)
+            C = recursive.fmm(a, L, A, B, peel=peel)
+            exact = classical.gemm_exact(A.tolist(), B.tolist())
+            assert C.tolist() == exact, (name, L, m, k, n)
+
+
+def test_recursive_planted_mistake_fails():
+    """Dropping a term of one W row (a plausible slip) breaks exactness."""
+    a = algorithms.strassen()
+    W = [list(r) for r in a.W]
+    W[0][3] = 0
+    bad = algorithms.Algorithm("bad", 2, 2, 2, 7, a.U, a.V, tuple(tuple(r) for r in W))
+    rng = random.Random(2)
+    A = _frac_matrix(rng, 4, 4)
+    B = _frac_matrix(rng, 4, 4)
+    assert recursive.fmm(bad, 1, A, B).tolist() != classical.gemm_exact(A.tolist(), B.tolist())
+
+
+def test_flop_closed_forms():
+    """F_C(N) = 2N^3 - N^2 and F_S(N) = 7 N^lg7 - 6 N^2 (Section 2.1) when the
+    recursion runs down to 1 x 1 blocks."""
+    for p in range(0, 5):
+        N = 2 ** p
+        A = np.ones((N, N))
+        cC = recursive.FlopCounter()
+        recursive.fmm(algorithms.classical_222(), p, A, A, counter=cC)
+        assert cC.flops == 2 * N ** 3 - N ** 2
+        cS = recursive.FlopCounter()
+        recursive.fmm(algorithms.strassen(), p, A, A, counter=cS)
+        assert cS.flops == 7 * round(N ** math.log2(7)) - 6 * N ** 2
+
+
+@pytest.mark.parametrize("name", ALGS)
+def test_recursive_integer_bit_exact_binary64(name):
+    """Integer inputs in {-8..8}: every intermediate is an integer far below
+    2^53, so binary64 O2 equals O1 bit for bit."""
+    a = algorithms.get(name)
+    rng = np.random.default_rng(4)
+    L = 2
+    m, k, n = a.M ** L * 5 + 1, a.K ** L * 4 + 2, a.N ** L * 3 + 1
+    A = rng.integers(-8, 9, (m, k)).astype(float)
+    B = rng.integers(-8, 9, (k, n)).astype(float)
+    ref = classical.gemm(A, B)
+    for peel in ("dynamic", "static"):
+        assert np.array_equal(recursive.fmm(a, L, A, B, peel=peel), ref)
+
+
+@pytest.mark.parametrize("name", ALGS)
+def test_recursive_float_close(name):
+    a = algorithms.get(name)
+    rng = np.random.default_rng(8)
+    m, k, n = 2 * a.M ** 2 * 7, 2 * a.K ** 2 * 7, 2 * a.N ** 2 * 7
+    A = rng.uniform(-1, 1, (m, k))
+    B = rng.uniform(-1, 1, (k, n))
+    ref = classical.gemm(A, B)
+    C = recursive.fmm(a, 2, A, B)
+    rel = np.linalg.norm(C - ref) / np.linalg.norm(ref)
+    assert rel < 1e-14
+    assert rel > 0  # the fast algorithm really rounds differently
+
+
+@pytest.mark.parametrize("name", ["strassen_222_7", "fmm_424_26"])
+def test_form_and_combine_reproduce_static_core(name):
+    """form_operands / combine_products (the stage-by-stage view used to check
+    the GPU addition kernels) reproduce the static-peel recursion bit for
+    bit on a divisible core."""
+    a = algorithms.get(name)
+    L = 2
+    rng = np.random.default_rng(9)
+    m, k, n = a.M ** L * 3, a.K ** L * 2, a.N ** L * 3
+    A = rng.uniform(-1, 1, (m, k))
+    B = rng.uniform(-1, 1, (k, n))
+    S = recursive.form_operands(a, L, A, "A")
+    T = recursive.form_operands(a, L, B, "B")
+    assert len(S) == a.R ** L
+    Ms = [classical.gemm(s, t) for s, t in zip(S, T)]
+    C = recursive.combine_products(a, L, Ms)
+    assert np.array_equal(C, recursive.fmm(a, L, A, B, peel="static"))
