@@ -1,0 +1,252 @@
+"""MI355X recursive fast matrix multiplication (Benson and Ballard, PPoPP 2015).
+
+A thin ctypes binding over the C ABI in ``include/fmm.h``: every step of the
+path (operand formation, grouped leaf GEMMs, W-combination) runs in the HIP
+kernels of ``libfmm.so``.  This module only marshals arguments; it raises
+``FmmError`` with the library's message on any non-zero status, and
+``ImportError`` if the built library is missing (there is no fallback).
+PyTorch supplies device memory and streams.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["FmmError", "Plan", "gemm", "algorithm_coeffs", "algorithm_names",
+           "check_algorithms", "library_path", "F64", "F32", "F32_BF16X3",
+           "STAGE_FORM_S", "STAGE_FORM_T", "STAGE_LEAF", "STAGE_COMBINE", "LOC_A", "LOC_B",
+           "LOC_C", "LOC_WORKSPACE"]
+
+F64, F32, F32_BF16X3 = 0, 1, 2
+STAGE_FORM_S, STAGE_FORM_T, STAGE_LEAF, STAGE_COMBINE = 0, 1, 2, 3
+LOC_A, LOC_B, LOC_C, LOC_WORKSPACE = 0, 1, 2, 3
+_DTYPE_NAMES = {"f64": F64, "float64": F64, "f32": F32, "float32": F32, "bf16x3": F32_BF16X3,
+                "f32_bf16x3": F32_BF16X3}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def library_path():
+    return os.path.join(_HERE, "libfmm.so")
+
+
+class FmmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fmm status {code}: {msg}")
+        self.code = code
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("k", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("levels", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("M", ctypes.c_int), ("K", ctypes.c_int), ("N", ctypes.c_int), ("R", ctypes.c_int),
+                ("m0", ctypes.c_int64), ("k0", ctypes.c_int64), ("n0", ctypes.c_int64),
+                ("leaf_m", ctypes.c_int64), ("leaf_k", ctypes.c_int64), ("leaf_n", ctypes.c_int64),
+                ("num_leaves", ctypes.c_int64), ("num_s_materialized", ctypes.c_int64),
+                ("num_t_materialized", ctypes.c_int64), ("num_gemm_problems", ctypes.c_int64),
+                ("gemm_tiles", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t),
+                ("leaf_flops", ctypes.c_double), ("classical_flops", ctypes.c_double),
+                ("add_bytes", ctypes.c_double), ("gemm_min_bytes", ctypes.c_double)]
+
+
+def _load():
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() "
+                          "or python paper_1409_2908_amd/build.py")
+    lib = ctypes.CDLL(path)
+    i64, i32, vp, dp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_double
+    P = ctypes.c_void_p
+    sig = {
+        "fmm_plan": ([ctypes.POINTER(P), ctypes.c_char_p, i64, i64, i64, i32, i32], i32),
+        "fmm_plan_host": ([ctypes.POINTER(P), ctypes.c_char_p, i64, i64, i64, i32, i32], i32),
+        "fmm_multiply": ([P, vp, i64, vp, i64, vp, i64, vp], i32),
+        "fmm_run_stage": ([P, i32, vp, i64, vp, i64, vp, i64, vp], i32),
+        "fmm_plan_operand": ([P, i32, i64, ctypes.POINTER(i32), ctypes.POINTER(i64),
+                              ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                              ctypes.POINTER(dp)], i32),
+        "fmm_plan_workspace": ([P], vp),
+        "fmm_plan_workspace_bytes": ([P], ctypes.c_size_t),
+        "fmm_plan_info": ([P, ctypes.POINTER(_Info)], i32),
+        "fmm_plan_enable_timing": ([P, i32], i32),
+        "fmm_plan_stage_ms": ([P, ctypes.POINTER(dp)], i32),
+        "fmm_plan_destroy": ([P], i32),
+        "fmm_gemm": ([i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp], i32),
+        "fmm_num_algorithms": ([], i32),
+        "fmm_algorithm_name": ([i32], ctypes.c_char_p),
+        "fmm_algorithm_coeffs": ([ctypes.c_char_p] + [ctypes.POINTER(i32)] * 4 + [vp] * 3, i32),
+        "fmm_check_algorithms": ([], i32),
+        "fmm_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status):
+    if status != 0:
+        raise FmmError(status, _lib.fmm_last_error().decode())
+
+
+def _dtype_code(dtype):
+    if isinstance(dtype, str):
+        return _DTYPE_NAMES[dtype]
+    return int(dtype)
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _mat(t, name, elt):
+    """(pointer, leading dimension) of a row-major (unit column stride) tensor."""
+    import torch
+    if t.dtype != elt:
+        raise TypeError(f"{name} must be {elt}, got {t.dtype}")
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+    if t.numel() and t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit column stride (row-major)")
+    if t.numel() and not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    ld = t.stride(0) if t.size(0) > 1 else max(t.size(1), 1)
+    return ctypes.c_void_p(t.data_ptr() if t.numel() else 0), max(ld, t.size(1))
+
+
+class Plan:
+    """A planned product C = A @ B (``fmm_plan``).  ``host_only`` plans
+    (``fmm_plan_host``) can be inspected but not run."""
+
+    def __init__(self, alg, m, k, n, levels, dtype=F64, host_only=False):
+        self._p = ctypes.c_void_p()
+        self.dtype = _dtype_code(dtype)
+        fn = _lib.fmm_plan_host if host_only else _lib.fmm_plan
+        _check(fn(ctypes.byref(self._p), alg.encode(), m, k, n, levels, self.dtype))
+        self.alg, self.m, self.k, self.n, self.levels = alg, m, k, n, levels
+        self.host_only = host_only
+
+    def _elt(self):
+        import torch
+        return torch.float64 if self.dtype == F64 else torch.float32
+
+    @property
+    def info(self):
+        inf = _Info()
+        _check(_lib.fmm_plan_info(self._p, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in _Info._fields_}
+
+    @property
+    def workspace_bytes(self):
+        return int(_lib.fmm_plan_workspace_bytes(self._p))
+
+    @property
+    def workspace_ptr(self):
+        return _lib.fmm_plan_workspace(self._p)
+
+    def _args(self, A, B, C):
+        import torch
+        elt = self._elt()
+        if C is None:
+            C = torch.empty((self.m, self.n), dtype=elt, device=A.device)
+        if tuple(A.shape) != (self.m, self.k) or tuple(B.shape) != (self.k, self.n) \
+                or tuple(C.shape) != (self.m, self.n):
+            raise ValueError(f"shapes {tuple(A.shape)} {tuple(B.shape)} {tuple(C.shape)} do not "
+                             f"match the plan ({self.m}, {self.k}, {self.n})")
+        a, lda = _mat(A, "A", elt)
+        b, ldb = _mat(B, "B", elt)
+        c, ldc = _mat(C, "C", elt)
+        return a, lda, b, ldb, c, ldc, C
+
+    def multiply(self, A, B, C=None, stream=None):
+        a, lda, b, ldb, c, ldc, C = self._args(A, B, C)
+        _check(_lib.fmm_multiply(self._p, a, lda, b, ldb, c, ldc, _stream_ptr(stream)))
+        return C
+
+    def run_stage(self, stage, A, B, C=None, stream=None):
+        a, lda, b, ldb, c, ldc, C = self._args(A, B, C)
+        _check(_lib.fmm_run_stage(self._p, stage, a, lda, b, ldb, c, ldc, _stream_ptr(stream)))
+        return C
+
+    def operand(self, side, leaf):
+        """(loc, offset, row, col, ld, alpha) of a leaf operand (fmm_plan_operand)."""
+        loc = ctypes.c_int()
+        off, row, col, ld = (ctypes.c_int64() for _ in range(4))
+        alpha = ctypes.c_double()
+        _check(_lib.fmm_plan_operand(self._p, side, leaf, ctypes.byref(loc), ctypes.byref(off),
+                                     ctypes.byref(row), ctypes.byref(col), ctypes.byref(ld),
+                                     ctypes.byref(alpha)))
+        return loc.value, off.value, row.value, col.value, ld.value, alpha.value
+
+    def enable_timing(self, on=True):
+        _check(_lib.fmm_plan_enable_timing(self._p, 1 if on else 0))
+
+    def stage_ms(self):
+        out = (ctypes.c_double * 4)()
+        _check(_lib.fmm_plan_stage_ms(self._p, out))
+        return list(out)
+
+    def close(self):
+        if self._p:
+            _check(_lib.fmm_plan_destroy(self._p))
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._p:
+                _lib.fmm_plan_destroy(self._p)
+                self._p = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def gemm(A, B, C=None, dtype=None, stream=None):
+    """Classical C = A @ B with the library's MFMA kernel (fmm_gemm)."""
+    import torch
+    if dtype is None:
+        dtype = F64 if A.dtype == torch.float64 else F32
+    dtype = _dtype_code(dtype)
+    elt = torch.float64 if dtype == F64 else torch.float32
+    m, k = A.shape
+    n = B.shape[1]
+    if C is None:
+        C = torch.empty((m, n), dtype=elt, device=A.device)
+    a, lda = _mat(A, "A", elt)
+    b, ldb = _mat(B, "B", elt)
+    c, ldc = _mat(C, "C", elt)
+    _check(_lib.fmm_gemm(dtype, m, k, n, a, lda, b, ldb, c, ldc, _stream_ptr(stream)))
+    return C
+
+
+def algorithm_names():
+    return [_lib.fmm_algorithm_name(i).decode() for i in range(_lib.fmm_num_algorithms())]
+
+
+def algorithm_coeffs(name):
+    """(M, K, N, R, U, V, W) of a compiled-in base case, U/V/W as int numpy arrays."""
+    dims = [ctypes.c_int() for _ in range(4)]
+    _check(_lib.fmm_algorithm_coeffs(name.encode(), *[ctypes.byref(d) for d in dims], None, None, None))
+    M, K, N, R = (d.value for d in dims)
+    U = np.zeros((M * K, R), dtype=np.int8)
+    V = np.zeros((K * N, R), dtype=np.int8)
+    W = np.zeros((M * N, R), dtype=np.int8)
+    _check(_lib.fmm_algorithm_coeffs(name.encode(), *[ctypes.byref(d) for d in dims],
+                                     U.ctypes.data, V.ctypes.data, W.ctypes.data))
+    return M, K, N, R, U.astype(int), V.astype(int), W.astype(int)
+
+
+def check_algorithms():
+    _check(_lib.fmm_check_algorithms())

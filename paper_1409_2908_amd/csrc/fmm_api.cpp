@@ -1,0 +1,488 @@
+// C ABI and executor: validates arguments, owns the device resources of a
+// plan, and enqueues the stages (operand formation, grouped leaf GEMM,
+// W-combination) on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/fmm.h"
+#include "fmm_internal.h"
+#include "fmm_launch.h"
+
+struct fmm_plan_s {
+  fmm::Plan P;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+fmm_status fail(fmm_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+fmm_status hip_fail(hipError_t e, const char* what) {
+  return fail(FMM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int num_cus(int device) {
+  static int cached[64] = {0};
+  if (device < 0 || device >= 64) return 256;
+  if (!cached[device]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || v <= 0)
+      v = 256;
+    cached[device] = v;
+  }
+  return cached[device];
+}
+
+// Exact Brent check of one table (Equation (2) against the tensor of
+// Section 2.2): sum_r U[i][r] V[j][r] W[k][r] == [A_i B_j contributes to C_k].
+bool brent_ok(const fmm::AlgInfo& a, std::string* why) {
+  const int MK = a.M * a.K, KN = a.K * a.N, MN = a.M * a.N, R = a.R;
+  for (int i = 0; i < MK; ++i)
+    for (int j = 0; j < KN; ++j)
+      for (int k = 0; k < MN; ++k) {
+        long long s = 0;
+        for (int r = 0; r < R; ++r) s += (long long)a.U[i * R + r] * a.V[j * R + r] * a.W[k * R + r];
+        const int ia = i / a.K, ib = i % a.K, jb = j / a.N, jc = j % a.N, ka = k / a.N, kc = k % a.N;
+        const long long t = (ib == jb && jc == kc && ia == ka) ? 1 : 0;
+        if (s != t) {
+          *why = std::string("table ") + a.name + " fails the Brent equation at (i,j,k)=(" +
+                 std::to_string(i) + "," + std::to_string(j) + "," + std::to_string(k) + ")";
+          return false;
+        }
+      }
+  return true;
+}
+
+fmm_status check_tables_once() {
+  static int state = 0;  // 0 unknown, 1 ok, 2 bad
+  static std::string why;
+  if (state == 0) {
+    state = 1;
+    for (int i = 0; i < fmm::kNumAlgorithms; ++i)
+      if (!brent_ok(fmm::alg_info(i), &why)) {
+        state = 2;
+        break;
+      }
+  }
+  return state == 1 ? FMM_OK : fail(FMM_EALG, why);
+}
+
+size_t elt_size(int elt) { return elt == fmm::ELT_F64 ? 8 : 4; }
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return abytes && bbytes && x < y + bbytes && y < x + abytes;
+}
+
+size_t span_bytes(int64_t rows, int64_t cols, int64_t ld, size_t es) {
+  if (rows <= 0 || cols <= 0) return 0;
+  return ((size_t)(rows - 1) * ld + cols) * es;
+}
+
+fmm_status validate(const fmm::Plan& P, const void* A, int64_t lda, const void* B, int64_t ldb,
+                    const void* C, int64_t ldc) {
+  if (P.m == 0 || P.n == 0) return FMM_OK;
+  if (!C) return fail(FMM_EINVAL, "C is NULL");
+  if (ldc < P.n) return fail(FMM_EINVAL, "ldc < n");
+  if (P.k > 0) {
+    if (!A || !B) return fail(FMM_EINVAL, "A or B is NULL");
+    if (lda < P.k) return fail(FMM_EINVAL, "lda < k");
+    if (ldb < P.n) return fail(FMM_EINVAL, "ldb < n");
+    const size_t es = elt_size(P.elt);
+    const size_t cb = span_bytes(P.m, P.n, ldc, es);
+    if (overlaps(C, cb, A, span_bytes(P.m, P.k, lda, es)) || overlaps(C, cb, B, span_bytes(P.k, P.n, ldb, es)))
+      return fail(FMM_EINVAL, "C overlaps A or B");
+  }
+  return FMM_OK;
+}
+
+fmm::Bases make_bases(const fmm::Plan& P, const void* A, int64_t lda, const void* B, int64_t ldb,
+                      void* C, int64_t ldc) {
+  fmm::Bases b;
+  b.ptr[0] = const_cast<void*>(A);
+  b.ptr[1] = const_cast<void*>(B);
+  b.ptr[2] = C;
+  b.ptr[3] = P.ws;
+  b.ld[0] = lda;
+  b.ld[1] = ldb;
+  b.ld[2] = ldc;
+  b.ld[3] = 0;
+  return b;
+}
+
+template <typename T>
+const T* table_ptr(const fmm::Plan& P, size_t off) {
+  return (const T*)((const char*)P.dev_table + off);
+}
+
+hipError_t run_form(const fmm::Plan& P, const std::vector<fmm::FormPass>& passes, const fmm::Bases& b,
+                    hipStream_t s) {
+  for (const fmm::FormPass& fp : passes) {
+    fmm::FormArgs a;
+    a.bases = b;
+    a.groups = table_ptr<fmm::Ref>(P, fp.dev_groups);
+    a.outs = table_ptr<int64_t>(P, fp.dev_outs);
+    a.h = fp.h;
+    a.w = fp.w;
+    a.out_ld = fp.out_ld;
+    a.out_elt = fp.out_elt;
+    a.nout = fp.nout;
+    hipError_t e = fmm::launch_form(P.alg_id, a, fp.side, fp.lv, fp.ngroups, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t run_leaf(const fmm::Plan& P, const fmm::Bases& b, hipStream_t s) {
+  if (P.gemm_groups.empty()) return hipSuccess;
+  fmm::GemmArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.bases = b;
+  a.probs = table_ptr<fmm::GemmProb>(P, P.dev_probs);
+  a.ngroups = (int)P.gemm_groups.size();
+  a.elt = P.elt;
+  a.total_tiles = P.gemm_tiles;
+  for (size_t i = 0; i < P.gemm_groups.size(); ++i) a.groups[i] = P.gemm_groups[i];
+  return fmm::launch_gemm(a, P.dtype, num_cus(P.device), s);
+}
+
+hipError_t run_combine(const fmm::Plan& P, const fmm::Bases& b, hipStream_t s) {
+  for (const fmm::CombinePass& cp : P.w_passes) {
+    fmm::CombineArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.bases = b;
+    a.in_off = table_ptr<int64_t>(P, cp.dev_in);
+    a.out = table_ptr<fmm::Ref>(P, cp.dev_out);
+    a.h = cp.h;
+    a.w = cp.w;
+    a.in_ld = cp.in_ld;
+    a.in_stride = cp.in_stride;
+    a.in_elt = cp.in_elt;
+    a.has_p = cp.has_p ? 1 : 0;
+    a.p = cp.p;
+    const fmm::AlgInfo& A = fmm::alg_info(P.alg_id);
+    for (int k = 0; k < A.M * A.N; ++k)
+      for (int r = 0; r < A.R; ++r) a.wc[k][r] = A.W[k * A.R + r];
+    hipError_t e = fmm::launch_combine(P.alg_id, a, cp.lv, cp.ngroups, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t run_stage(const fmm::Plan& P, int stage, const fmm::Bases& b, hipStream_t s) {
+  switch (stage) {
+    case FMM_STAGE_FORM_S: return run_form(P, P.s_passes, b, s);
+    case FMM_STAGE_FORM_T: return run_form(P, P.t_passes, b, s);
+    case FMM_STAGE_LEAF: return run_leaf(P, b, s);
+    case FMM_STAGE_COMBINE: return run_combine(P, b, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
+                       int dtype, bool device) {
+  if (!out) return fail(FMM_EINVAL, "out is NULL");
+  *out = nullptr;
+  fmm_status st = check_tables_once();
+  if (st != FMM_OK) return st;
+  if (dtype == FMM_F32_BF16X3 && !fmm::kHaveBf16x3)
+    return fail(FMM_EUNSUPPORTED, "BF16x3 leaves are not available in this build");
+  fmm_plan_s* h = new (std::nothrow) fmm_plan_s();
+  if (!h) return fail(FMM_ENOMEM, "host allocation failed");
+  int code = 0;
+  std::string err = fmm::make_plan(h->P, alg, m, k, n, levels, dtype, &code);
+  if (!err.empty()) {
+    delete h;
+    return fail((fmm_status)code, err);
+  }
+  fmm::Plan& P = h->P;
+  if (device) {
+    if (const char* bud = std::getenv("FMM_HBM_BUDGET")) {
+      const double budget = std::atof(bud);
+      if (budget > 0 && (double)P.ws_bytes > budget) {
+        delete h;
+        return fail(FMM_ENOMEM, "workspace of " + std::to_string(P.ws_bytes) +
+                                    " bytes exceeds FMM_HBM_BUDGET");
+      }
+    }
+    hipError_t e = hipGetDevice(&P.device);
+    if (e != hipSuccess) {
+      delete h;
+      return hip_fail(e, "hipGetDevice");
+    }
+    if (P.ws_bytes) {
+      e = hipMalloc(&P.ws, P.ws_bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        P.ws = nullptr;
+        delete h;
+        return fail(FMM_ENOMEM, "hipMalloc of " + std::to_string(P.ws_bytes) + " workspace bytes failed");
+      }
+    }
+    e = hipMalloc(&P.dev_table, P.table_bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      if (P.ws) (void)hipFree(P.ws);
+      delete h;
+      return fail(FMM_ENOMEM, "hipMalloc of the descriptor table failed");
+    }
+    e = hipMemcpy(P.dev_table, P.table.data(), P.table_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      if (P.ws) (void)hipFree(P.ws);
+      (void)hipFree(P.dev_table);
+      delete h;
+      return hip_fail(e, "hipMemcpy of the descriptor table");
+    }
+    P.host_only = false;
+  }
+  *out = h;
+  return FMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fmm_status fmm_plan(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
+                    int dtype) {
+  return plan_common(out, alg, m, k, n, levels, dtype, true);
+}
+
+fmm_status fmm_plan_host(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, int64_t n,
+                         int levels, int dtype) {
+  return plan_common(out, alg, m, k, n, levels, dtype, false);
+}
+
+fmm_status fmm_run_stage(fmm_plan_t p, int stage, const void* A, int64_t lda, const void* B,
+                         int64_t ldb, void* C, int64_t ldc, void* stream) {
+  if (!p) return fail(FMM_EINVAL, "plan is NULL");
+  const fmm::Plan& P = p->P;
+  if (P.host_only) return fail(FMM_EINVAL, "host-only plan cannot run");
+  if (stage < 0 || stage >= FMM_NUM_STAGES) return fail(FMM_EINVAL, "bad stage");
+  fmm_status st = validate(P, A, lda, B, ldb, C, ldc);
+  if (st != FMM_OK) return st;
+  if (P.m == 0 || P.n == 0) return FMM_OK;
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  if (cur != P.device) return fail(FMM_EINVAL, "plan belongs to another device");
+  const fmm::Bases b = make_bases(P, A, lda, B, ldb, C, ldc);
+  hipError_t e = run_stage(P, stage, b, (hipStream_t)stream);
+  return e == hipSuccess ? FMM_OK : hip_fail(e, "kernel launch");
+}
+
+fmm_status fmm_multiply(fmm_plan_t p, const void* A, int64_t lda, const void* B, int64_t ldb,
+                        void* C, int64_t ldc, void* stream) {
+  if (!p) return fail(FMM_EINVAL, "plan is NULL");
+  fmm::Plan& P = p->P;
+  if (P.host_only) return fail(FMM_EINVAL, "host-only plan cannot run");
+  fmm_status st = validate(P, A, lda, B, ldb, C, ldc);
+  if (st != FMM_OK) return st;
+  if (P.m == 0 || P.n == 0) return FMM_OK;
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  if (cur != P.device) return fail(FMM_EINVAL, "plan belongs to another device");
+  const fmm::Bases b = make_bases(P, A, lda, B, ldb, C, ldc);
+  hipStream_t s = (hipStream_t)stream;
+  for (int stage = 0; stage < FMM_NUM_STAGES; ++stage) {
+    if (P.timing) {
+      hipError_t e = hipEventRecord((hipEvent_t)P.events[stage], s);
+      if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
+    hipError_t e = run_stage(P, stage, b, s);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  }
+  if (P.timing) {
+    hipError_t e = hipEventRecord((hipEvent_t)P.events[FMM_NUM_STAGES], s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    P.timed_once = true;
+  }
+  return FMM_OK;
+}
+
+fmm_status fmm_plan_enable_timing(fmm_plan_t p, int enable) {
+  if (!p) return fail(FMM_EINVAL, "plan is NULL");
+  fmm::Plan& P = p->P;
+  if (P.host_only) return fail(FMM_EINVAL, "host-only plan");
+  if (enable && !P.events[0]) {
+    for (int i = 0; i <= FMM_NUM_STAGES; ++i) {
+      hipEvent_t ev;
+      hipError_t e = hipEventCreate(&ev);
+      if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+      P.events[i] = ev;
+    }
+  }
+  P.timing = enable != 0;
+  P.timed_once = false;
+  return FMM_OK;
+}
+
+fmm_status fmm_plan_stage_ms(fmm_plan_t p, double ms[FMM_NUM_STAGES]) {
+  if (!p || !ms) return fail(FMM_EINVAL, "NULL argument");
+  fmm::Plan& P = p->P;
+  if (!P.timed_once) return fail(FMM_EINVAL, "no timed multiply yet");
+  hipError_t e = hipEventSynchronize((hipEvent_t)P.events[FMM_NUM_STAGES]);
+  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  for (int i = 0; i < FMM_NUM_STAGES; ++i) {
+    float f = 0;
+    e = hipEventElapsedTime(&f, (hipEvent_t)P.events[i], (hipEvent_t)P.events[i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    ms[i] = f;
+  }
+  return FMM_OK;
+}
+
+fmm_status fmm_plan_operand(fmm_plan_t p, int side, int64_t leaf, int* loc, int64_t* offset,
+                            int64_t* row, int64_t* col, int64_t* ld, double* alpha) {
+  if (!p) return fail(FMM_EINVAL, "plan is NULL");
+  const fmm::Plan& P = p->P;
+  if (leaf < 0 || leaf >= (int64_t)P.leaves.size()) return fail(FMM_EINVAL, "leaf out of range");
+  if (side < 0 || side > 2) return fail(FMM_EINVAL, "side must be 0, 1 or 2");
+  const fmm::LeafRef& L = P.leaves[leaf];
+  const fmm::Ref& r = side == 0 ? L.s : side == 1 ? L.t : L.m;
+  const bool ws = r.buf == fmm::BUF_WS;
+  if (loc) *loc = r.buf;
+  if (offset) *offset = ws ? r.off + r.row * r.ld + r.col : 0;
+  if (row) *row = ws ? 0 : r.row;
+  if (col) *col = ws ? 0 : r.col;
+  if (ld) *ld = ws ? r.ld : 0;
+  if (alpha) *alpha = r.alpha;
+  return FMM_OK;
+}
+
+void* fmm_plan_workspace(fmm_plan_t p) { return p ? p->P.ws : nullptr; }
+
+size_t fmm_plan_workspace_bytes(fmm_plan_t p) { return p ? p->P.ws_bytes : 0; }
+
+fmm_status fmm_plan_info(fmm_plan_t p, fmm_plan_info_t* info) {
+  if (!p || !info) return fail(FMM_EINVAL, "NULL argument");
+  const fmm::Plan& P = p->P;
+  std::memset(info, 0, sizeof(*info));
+  info->m = P.m;
+  info->k = P.k;
+  info->n = P.n;
+  info->levels = P.levels;
+  info->dtype = P.dtype;
+  info->M = P.M;
+  info->K = P.K;
+  info->N = P.N;
+  info->R = P.R;
+  info->m0 = P.m0;
+  info->k0 = P.k0;
+  info->n0 = P.n0;
+  info->leaf_m = P.ml;
+  info->leaf_k = P.kl;
+  info->leaf_n = P.nl;
+  info->num_leaves = (int64_t)P.leaves.size();
+  info->num_s_materialized = P.s_mat;
+  info->num_t_materialized = P.t_mat;
+  info->num_gemm_problems = (int64_t)P.gemm_probs.size();
+  info->gemm_tiles = P.gemm_tiles;
+  info->workspace_bytes = P.ws_bytes;
+  info->leaf_flops = P.leaf_flops;
+  info->classical_flops = 2.0 * (double)P.m * (double)P.k * (double)P.n;
+  info->add_bytes = P.add_bytes;
+  info->gemm_min_bytes = P.gemm_min_bytes;
+  return FMM_OK;
+}
+
+fmm_status fmm_plan_destroy(fmm_plan_t p) {
+  if (!p) return FMM_OK;
+  fmm::Plan& P = p->P;
+  fmm_status st = FMM_OK;
+  if (!P.host_only) {
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (prev != P.device) (void)hipSetDevice(P.device);
+    if (P.ws && hipFree(P.ws) != hipSuccess) st = fail(FMM_EHIP, "hipFree of the workspace failed");
+    if (P.dev_table && hipFree(P.dev_table) != hipSuccess) st = fail(FMM_EHIP, "hipFree of the table failed");
+    for (void* ev : P.events)
+      if (ev) (void)hipEventDestroy((hipEvent_t)ev);
+    if (prev != P.device && prev >= 0) (void)hipSetDevice(prev);
+  }
+  delete p;
+  return st;
+}
+
+fmm_status fmm_gemm(int dtype, int64_t m, int64_t k, int64_t n, const void* A, int64_t lda,
+                    const void* B, int64_t ldb, void* C, int64_t ldc, void* stream) {
+  if (m < 0 || k < 0 || n < 0) return fail(FMM_EINVAL, "sizes must be non-negative");
+  if (dtype < 0 || dtype > 2) return fail(FMM_EINVAL, "unknown dtype");
+  if (dtype == FMM_F32_BF16X3 && !fmm::kHaveBf16x3)
+    return fail(FMM_EUNSUPPORTED, "BF16x3 leaves are not available in this build");
+  fmm::Plan P;
+  P.m = m;
+  P.k = k;
+  P.n = n;
+  P.dtype = dtype;
+  P.elt = dtype == 0 ? fmm::ELT_F64 : fmm::ELT_F32;
+  fmm_status st = validate(P, A, lda, B, ldb, C, ldc);
+  if (st != FMM_OK) return st;
+  if (m == 0 || n == 0) return FMM_OK;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  fmm::GemmArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.bases = make_bases(P, A, lda, B, ldb, C, ldc);
+  a.probs = nullptr;
+  a.single.a = fmm::Ref{fmm::BUF_A, P.elt, 0, 0, 0, 0, 1.0};
+  a.single.b = fmm::Ref{fmm::BUF_B, P.elt, 0, 0, 0, 0, 1.0};
+  a.single.c = fmm::Ref{fmm::BUF_C, P.elt, 0, 0, 0, 0, 1.0};
+  a.single.alpha = 1.0;
+  a.ngroups = 1;
+  a.elt = P.elt;
+  fmm::GemmGroup& g = a.groups[0];
+  g.m = m;
+  g.n = n;
+  g.k = k;
+  g.count = 1;
+  g.tiles_m = (m + fmm::kTileM - 1) / fmm::kTileM;
+  g.tiles_n = (n + fmm::kTileN - 1) / fmm::kTileN;
+  g.tile_start = 0;
+  g.prob_start = 0;
+  a.total_tiles = g.tiles_m * g.tiles_n;
+  hipError_t e = fmm::launch_gemm(a, dtype, num_cus(dev), (hipStream_t)stream);
+  return e == hipSuccess ? FMM_OK : hip_fail(e, "kernel launch");
+}
+
+int fmm_num_algorithms(void) { return fmm::kNumAlgorithms; }
+
+const char* fmm_algorithm_name(int index) {
+  if (index < 0 || index >= fmm::kNumAlgorithms) return nullptr;
+  return fmm::alg_info(index).name;
+}
+
+fmm_status fmm_algorithm_coeffs(const char* alg, int* M, int* K, int* N, int* R, int8_t* U, int8_t* V,
+                                int8_t* W) {
+  const int id = fmm::find_algorithm(alg);
+  if (id < 0) return fail(FMM_EALG, std::string("unknown algorithm '") + (alg ? alg : "(null)") + "'");
+  const fmm::AlgInfo& a = fmm::alg_info(id);
+  if (M) *M = a.M;
+  if (K) *K = a.K;
+  if (N) *N = a.N;
+  if (R) *R = a.R;
+  if (U) std::memcpy(U, a.U, (size_t)a.M * a.K * a.R);
+  if (V) std::memcpy(V, a.V, (size_t)a.K * a.N * a.R);
+  if (W) std::memcpy(W, a.W, (size_t)a.M * a.N * a.R);
+  return FMM_OK;
+}
+
+fmm_status fmm_check_algorithms(void) {
+  std::string why;
+  for (int i = 0; i < fmm::kNumAlgorithms; ++i)
+    if (!brent_ok(fmm::alg_info(i), &why)) return fail(FMM_EALG, why);
+  return FMM_OK;
+}
+
+const char* fmm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

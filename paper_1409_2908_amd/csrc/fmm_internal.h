@@ -1,0 +1,174 @@
+// Internal structures shared by the planner (host) and the kernels (device).
+#pragma once
+
+#include <cstdint>
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "fmm_tables.h"
+
+namespace fmm {
+
+// Buffers a descriptor can point into.  A, B and C are the caller's operands
+// (their leading dimensions arrive with each multiply); WS is the workspace.
+enum Buf : int32_t { BUF_A = 0, BUF_B = 1, BUF_C = 2, BUF_WS = 3, BUF_NONE = -1 };
+
+// Element type of a buffer region.
+enum Elt : int32_t { ELT_F64 = 0, ELT_F32 = 1 };
+
+// A strided matrix view: element (i, j) is at
+//   base[buf] + off + (row + i) * LD + (col + j),  LD = ld[buf] for A/B/C, else ld.
+// alpha scales every element read through the view (single-non-zero columns of
+// U or V become such views instead of copies).
+struct Ref {
+  int32_t buf;
+  int32_t elt;
+  int64_t off;
+  int64_t row;
+  int64_t col;
+  int64_t ld;
+  double alpha;
+};
+
+struct Bases {
+  void* ptr[4];
+  int64_t ld[4];
+};
+
+// One pass of operand formation: every group has one source view and R^lv
+// outputs (workspace element offsets, -1 where the output is a view instead).
+// Output element (p, q) of output o of group g is
+//   sum over the lv-level Kronecker product of the side's coefficient matrix
+//   applied to the (BR*BC)^lv blocks of the group's source at position (p, q).
+struct FormPass {
+  int side;       // 0: A side (U, blocks M x K); 1: B side (V, blocks K x N)
+  int lv;         // levels fused in this pass (1 or 2)
+  int depth_in;   // depth of the sources (0 = the input matrix)
+  int64_t h, w;   // output block dims = position grid
+  int64_t out_ld;
+  int out_elt;
+  int ngroups;
+  int nout;       // R^lv
+  std::vector<Ref> groups;
+  std::vector<int64_t> outs;  // ngroups * nout
+  size_t dev_groups = 0, dev_outs = 0;  // byte offsets in the plan's device table
+};
+
+// One pass of the W-combination: group g reads R^lv inputs laid out at
+// in_off + r * in_stride (r in leaf order, ld in_ld) and writes one output
+// matrix of (BR^lv h) x (BC^lv w) through `out`.  The last pass (depth 0)
+// writes C and adds the k-peel product P when present.
+struct CombinePass {
+  int lv;
+  int depth_in;
+  int64_t h, w;
+  int in_elt;
+  int64_t in_ld, in_stride;
+  int ngroups;
+  std::vector<int64_t> in_off;  // per group
+  std::vector<Ref> out;         // per group
+  bool has_p = false;
+  Ref p;                        // k-peel product (m0 x n0) when has_p
+  size_t dev_in = 0, dev_out = 0;
+};
+
+struct GemmProb {
+  Ref a, b, c;
+  double alpha;
+  double pad;
+};
+
+// Problems of identical shape; tiles of all groups form one flat index space.
+struct GemmGroup {
+  int64_t m, n, k;
+  int64_t count;
+  int64_t tiles_m, tiles_n;
+  int64_t tile_start;  // first flat tile index of this group
+  int64_t prob_start;  // index of the group's first problem in the problem array
+};
+
+constexpr int kMaxGemmGroups = 8;
+
+struct GemmArgs {
+  Bases bases;
+  const GemmProb* probs;  // device array; NULL means the single problem below
+  GemmProb single;
+  int ngroups;
+  int elt;
+  int64_t total_tiles;
+  GemmGroup groups[kMaxGemmGroups];
+};
+
+struct FormArgs {
+  Bases bases;
+  const Ref* groups;
+  const int64_t* outs;
+  int64_t h, w, out_ld;
+  int out_elt;
+  int nout;
+};
+
+constexpr int kMaxMN = 16, kMaxR = 32;
+
+struct CombineArgs {
+  Bases bases;
+  const int64_t* in_off;
+  const Ref* out;
+  int64_t h, w, in_ld, in_stride;
+  int in_elt;
+  int has_p;
+  Ref p;
+  signed char wc[kMaxMN][kMaxR];  // W[k][r] for kernels that index it at run time
+};
+
+// --- plan -----------------------------------------------------------------
+
+struct LeafRef {
+  Ref s, t, m;
+};
+
+struct Plan {
+  int alg_id = -1;  // -1: classical (no recursion)
+  int M = 1, K = 1, N = 1, R = 1;
+  int64_t m = 0, k = 0, n = 0;
+  int levels = 0;
+  int dtype = 0;
+  int elt = ELT_F64;  // element type of A, B, C and the leaf operands
+  int64_t m0 = 0, k0 = 0, n0 = 0, ml = 0, kl = 0, nl = 0;
+
+  std::vector<FormPass> s_passes, t_passes;
+  std::vector<CombinePass> w_passes;
+  std::vector<GemmGroup> gemm_groups;
+  std::vector<GemmProb> gemm_probs;
+  std::vector<LeafRef> leaves;
+  int64_t gemm_tiles = 0;
+  int64_t s_mat = 0, t_mat = 0;
+
+  size_t ws_bytes = 0;
+  size_t table_bytes = 0;
+  std::vector<unsigned char> table;  // host image of the device descriptor table
+  size_t dev_probs = 0;
+
+  // device side
+  bool host_only = true;
+  int device = -1;
+  void* ws = nullptr;
+  void* dev_table = nullptr;
+  bool timing = false;
+  void* events[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool timed_once = false;
+
+  double leaf_flops = 0, add_bytes = 0, gemm_min_bytes = 0;
+};
+
+// Plans on the host only; fills every field above except the device side.
+// Returns an empty string on success, else the error message (and sets *code).
+std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
+                      int dtype, int* code);
+
+int find_algorithm(const char* name);  // -1 for "classical", -2 unknown
+
+constexpr int64_t kTileM = 128, kTileN = 128;
+
+}  // namespace fmm

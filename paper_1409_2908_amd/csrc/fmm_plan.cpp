@@ -1,0 +1,399 @@
+// Planner: static peeling, the operand tree with single-non-zero views, the
+// pass schedule of the addition kernels, the workspace layout and the grouped
+// GEMM problem list.  Host-only code; no HIP calls.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+
+namespace {
+
+int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+size_t elt_size(int elt) { return elt == ELT_F64 ? 8 : 4; }
+
+struct Arena {
+  size_t used = 0;
+  // Returns the byte offset of a fresh 256-byte aligned region.
+  size_t alloc(size_t bytes) {
+    size_t off = round_up((int64_t)used, 256);
+    used = off + bytes;
+    return off;
+  }
+};
+
+// Number of non-zeros in column r of a (rows x R) coefficient table, and the
+// row of the last one.
+int col_nnz(const signed char* X, int rows, int R, int r, int* where, int* coef) {
+  int cnt = 0;
+  for (int i = 0; i < rows; ++i) {
+    if (X[i * R + r] != 0) {
+      ++cnt;
+      *where = i;
+      *coef = X[i * R + r];
+    }
+  }
+  return cnt;
+}
+
+// Levels fused per addition pass (1 or 2); FMM_FUSE overrides.
+int fuse_levels() {
+  const char* e = std::getenv("FMM_FUSE");
+  if (e && (e[0] == '1' || e[0] == '2') && e[1] == 0) return e[0] - '0';
+  return 1;
+}
+
+// Splits L levels into passes of at most `fuse` levels.  Operand formation
+// runs top-down and keeps the fused pass at the bottom (fewest bytes: the
+// R^L outputs are written once); the combination runs bottom-up with the
+// fused pass first, for the same reason.
+std::vector<int> schedule(int L, int fuse, bool top_down) {
+  std::vector<int> s;
+  int rest = L;
+  while (rest > 0) {
+    int lv = rest >= fuse ? fuse : rest;
+    if (top_down && rest > fuse) lv = 1;
+    s.push_back(lv);
+    rest -= lv;
+  }
+  return s;
+}
+
+struct Node {
+  Ref ref;
+};
+
+// Builds the operand-formation passes of one side.  Returns leaf refs.
+std::vector<Ref> plan_side(Plan& P, int side, Arena& ws, std::vector<FormPass>& passes,
+                           int64_t* materialized, double* bytes) {
+  const AlgInfo& A = alg_info(P.alg_id);
+  const int BR = side == 0 ? A.M : A.K;
+  const int BC = side == 0 ? A.K : A.N;
+  const int NB = BR * BC;
+  const int R = A.R;
+  const signed char* coef = side == 0 ? A.U : A.V;
+  const int64_t rows0 = side == 0 ? P.m0 : P.k0;
+  const int64_t cols0 = side == 0 ? P.k0 : P.n0;
+  const int in_elt = P.elt;
+
+  std::vector<Ref> nodes(1);
+  nodes[0] = Ref{side == 0 ? BUF_A : BUF_B, in_elt, 0, 0, 0, 0, 1.0};
+  int depth = 0;
+  *materialized = 0;
+  for (int lv : schedule(P.levels, fuse_levels(), true)) {
+    const int d2 = depth + lv;
+    const bool final_pass = d2 == P.levels;
+    FormPass fp;
+    fp.side = side;
+    fp.lv = lv;
+    fp.depth_in = depth;
+    fp.h = rows0 / ipow(BR, d2);
+    fp.w = cols0 / ipow(BC, d2);
+    fp.out_ld = round_up(fp.w, 16);
+    fp.out_elt = final_pass ? P.elt : ELT_F64;
+    fp.ngroups = (int)nodes.size();
+    fp.nout = (int)ipow(R, lv);
+    const size_t region = (size_t)fp.h * fp.out_ld * elt_size(fp.out_elt);
+    std::vector<Ref> next;
+    next.reserve(nodes.size() * fp.nout);
+    for (const Ref& g : nodes) {
+      fp.groups.push_back(g);
+      *bytes += (double)ipow(NB, lv) * fp.h * fp.w * elt_size(g.elt);
+      for (int o = 0; o < fp.nout; ++o) {
+        // digits r_1..r_lv of o, r_1 most significant
+        int digits[8];
+        int t = o;
+        for (int j = lv - 1; j >= 0; --j) {
+          digits[j] = t % R;
+          t /= R;
+        }
+        bool single = true;
+        double alpha = g.alpha;
+        int64_t row = g.row, col = g.col;
+        for (int j = 0; j < lv && single; ++j) {
+          int where = 0, c = 0;
+          if (col_nnz(coef, NB, R, digits[j], &where, &c) != 1) {
+            single = false;
+            break;
+          }
+          alpha *= c;
+          const int64_t bh = rows0 / ipow(BR, depth + j + 1);
+          const int64_t bw = cols0 / ipow(BC, depth + j + 1);
+          row += (int64_t)(where / BC) * bh;
+          col += (int64_t)(where % BC) * bw;
+        }
+        const bool view_ok = single && (!final_pass || g.elt == P.elt);
+        if (view_ok) {
+          Ref v = g;
+          v.alpha = alpha;
+          v.row = row;
+          v.col = col;
+          next.push_back(v);
+          fp.outs.push_back(-1);
+        } else {
+          const size_t off = ws.alloc(region);
+          Ref v{BUF_WS, fp.out_elt, (int64_t)(off / elt_size(fp.out_elt)), 0, 0, fp.out_ld, 1.0};
+          next.push_back(v);
+          fp.outs.push_back(v.off);
+          *bytes += (double)fp.h * fp.w * elt_size(fp.out_elt);
+          if (final_pass) ++*materialized;
+        }
+      }
+    }
+    passes.push_back(std::move(fp));
+    nodes.swap(next);
+    depth = d2;
+  }
+  return nodes;
+}
+
+}  // namespace
+
+int find_algorithm(const char* name) {
+  if (!name) return -2;
+  if (std::strcmp(name, "classical") == 0) return -1;
+  for (int i = 0; i < kNumAlgorithms; ++i)
+    if (std::strcmp(alg_info(i).name, name) == 0) return i;
+  return -2;
+}
+
+std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
+                      int dtype, int* code) {
+  *code = 1;  // FMM_EINVAL
+  if (m < 0 || k < 0 || n < 0) return "sizes must be non-negative";
+  if (levels < 0 || levels > 6) return "levels must be in [0, 6]";
+  if (dtype < 0 || dtype > 2) return "unknown dtype";
+  const int id = find_algorithm(alg);
+  if (id == -2) {
+    *code = 5;  // FMM_EALG
+    return std::string("unknown algorithm '") + (alg ? alg : "(null)") + "'";
+  }
+  P = Plan();
+  P.m = m;
+  P.k = k;
+  P.n = n;
+  P.dtype = dtype;
+  P.elt = dtype == 0 ? ELT_F64 : ELT_F32;
+  const size_t es = elt_size(P.elt);
+  P.alg_id = id;
+  P.levels = id < 0 ? 0 : levels;
+  if (m == 0 || n == 0 || k == 0) P.levels = 0;  // nothing to recurse on
+  if (P.levels > 0) {
+    const AlgInfo& A = alg_info(id);
+    P.M = A.M;
+    P.K = A.K;
+    P.N = A.N;
+    P.R = A.R;
+    const int64_t fm = ipow(A.M, P.levels), fk = ipow(A.K, P.levels), fn = ipow(A.N, P.levels);
+    P.m0 = m / fm * fm;
+    P.k0 = k / fk * fk;
+    P.n0 = n / fn * fn;
+    P.ml = P.m0 / fm;
+    P.kl = P.k0 / fk;
+    P.nl = P.n0 / fn;
+    if (P.ml < 1 || P.kl < 1 || P.nl < 1)
+      return "recursion depth leaves a leaf dimension < 1 (m, k or n smaller than M^L, K^L or N^L)";
+  } else {
+    P.m0 = m;
+    P.k0 = k;
+    P.n0 = n;
+    P.ml = m;
+    P.kl = k;
+    P.nl = n;
+  }
+
+  Arena ws;
+  double add_bytes = 0;
+  const Ref refA{BUF_A, P.elt, 0, 0, 0, 0, 1.0};
+  const Ref refB{BUF_B, P.elt, 0, 0, 0, 0, 1.0};
+  const Ref refC{BUF_C, P.elt, 0, 0, 0, 0, 1.0};
+
+  if (P.levels > 0) {
+    const int L = P.levels, R = P.R;
+    std::vector<Ref> S = plan_side(P, 0, ws, P.s_passes, &P.s_mat, &add_bytes);
+    std::vector<Ref> T = plan_side(P, 1, ws, P.t_passes, &P.t_mat, &add_bytes);
+    const int64_t nleaves = ipow(R, L);
+    // Leaf products M_rho, contiguous with a uniform stride.
+    const int64_t m_ld = round_up(P.nl, 16);
+    const int64_t m_stride = round_up(P.ml * m_ld * (int64_t)es, 256) / (int64_t)es;
+    const size_t m_base = ws.alloc((size_t)m_stride * es * nleaves);
+    GemmGroup g0{P.ml, P.nl, P.kl, nleaves, 0, 0, 0, 0};
+    P.gemm_groups.push_back(g0);
+    for (int64_t r = 0; r < nleaves; ++r) {
+      GemmProb pr{};
+      pr.a = S[r];
+      pr.b = T[r];
+      pr.alpha = S[r].alpha * T[r].alpha;
+      pr.a.alpha = 1.0;
+      pr.b.alpha = 1.0;
+      pr.c = Ref{BUF_WS, P.elt, (int64_t)(m_base / es) + r * m_stride, 0, 0, m_ld, 1.0};
+      P.gemm_probs.push_back(pr);
+      P.leaves.push_back(LeafRef{S[r], T[r], pr.c});
+    }
+    // Peel problems (classical, Section 3.5).
+    Ref pref{};
+    bool has_p = false;
+    if (P.k0 < k) {
+      const int64_t p_ld = round_up(P.n0, 16);
+      const size_t off = ws.alloc((size_t)P.m0 * p_ld * es);
+      pref = Ref{BUF_WS, P.elt, (int64_t)(off / es), 0, 0, p_ld, 1.0};
+      has_p = true;
+      GemmProb pr{};
+      pr.a = refA;
+      pr.a.col = P.k0;
+      pr.b = refB;
+      pr.b.row = P.k0;
+      pr.c = pref;
+      pr.alpha = 1.0;
+      P.gemm_groups.push_back(GemmGroup{P.m0, P.n0, k - P.k0, 1, 0, 0, 0, 0});
+      P.gemm_probs.push_back(pr);
+    }
+    if (P.n0 < n) {
+      GemmProb pr{};
+      pr.a = refA;
+      pr.b = refB;
+      pr.b.col = P.n0;
+      pr.c = refC;
+      pr.c.col = P.n0;
+      pr.alpha = 1.0;
+      P.gemm_groups.push_back(GemmGroup{P.m0, n - P.n0, k, 1, 0, 0, 0, 0});
+      P.gemm_probs.push_back(pr);
+    }
+    if (P.m0 < m) {
+      GemmProb pr{};
+      pr.a = refA;
+      pr.a.row = P.m0;
+      pr.b = refB;
+      pr.c = refC;
+      pr.c.row = P.m0;
+      pr.alpha = 1.0;
+      P.gemm_groups.push_back(GemmGroup{m - P.m0, n, k, 1, 0, 0, 0, 0});
+      P.gemm_probs.push_back(pr);
+    }
+    // Combination passes, deepest level first.
+    std::vector<int64_t> node_off(nleaves);
+    for (int64_t r = 0; r < nleaves; ++r) node_off[r] = (int64_t)(m_base / es) + r * m_stride;
+    int64_t node_stride = m_stride, node_ld = m_ld;
+    int node_elt = P.elt;
+    int depth = L;
+    std::vector<int> sched = schedule(L, fuse_levels(), false);
+    for (size_t pi = 0; pi < sched.size(); ++pi) {
+      const int lv = sched[pi];
+      const int d2 = depth - lv;
+      CombinePass cp;
+      cp.lv = lv;
+      cp.depth_in = depth;
+      cp.h = P.m0 / ipow(P.M, depth);
+      cp.w = P.n0 / ipow(P.N, depth);
+      cp.in_elt = node_elt;
+      cp.in_ld = node_ld;
+      cp.in_stride = node_stride;
+      const int64_t ngroups = ipow(R, d2);
+      const int64_t per = ipow(R, lv);
+      cp.ngroups = (int)ngroups;
+      add_bytes += (double)ngroups * per * cp.h * cp.w * elt_size(node_elt);
+      const int64_t oh = cp.h * ipow(P.M, lv), ow = cp.w * ipow(P.N, lv);
+      std::vector<int64_t> next_off;
+      if (d2 == 0) {
+        cp.in_off.push_back(node_off[0]);
+        cp.out.push_back(refC);
+        if (has_p) {
+          cp.has_p = true;
+          cp.p = pref;
+          add_bytes += (double)P.m0 * P.n0 * es;
+        }
+        add_bytes += (double)P.m0 * P.n0 * es;
+      } else {
+        const int64_t o_ld = round_up(ow, 16);
+        const int64_t o_stride = round_up(oh * o_ld * 8, 256) / 8;
+        const size_t base = ws.alloc((size_t)o_stride * 8 * ngroups);
+        for (int64_t g = 0; g < ngroups; ++g) {
+          cp.in_off.push_back(node_off[g * per]);
+          const int64_t off = (int64_t)(base / 8) + g * o_stride;
+          cp.out.push_back(Ref{BUF_WS, ELT_F64, off, 0, 0, o_ld, 1.0});
+          next_off.push_back(off);
+          add_bytes += (double)oh * ow * 8;
+        }
+        node_stride = o_stride;
+        node_ld = o_ld;
+        node_elt = ELT_F64;
+      }
+      P.w_passes.push_back(std::move(cp));
+      node_off.swap(next_off);
+      depth = d2;
+    }
+  } else if (m > 0 && n > 0) {
+    GemmProb pr{};
+    pr.a = refA;
+    pr.b = refB;
+    pr.c = refC;
+    pr.alpha = 1.0;
+    P.gemm_groups.push_back(GemmGroup{m, n, k, 1, 0, 0, 0, 0});
+    P.gemm_probs.push_back(pr);
+  }
+  if (P.gemm_groups.size() > (size_t)kMaxGemmGroups) return "too many GEMM groups";
+
+  // Tiles and flop/byte accounting.
+  int64_t tiles = 0, prob = 0;
+  for (GemmGroup& g : P.gemm_groups) {
+    g.tiles_m = (g.m + kTileM - 1) / kTileM;
+    g.tiles_n = (g.n + kTileN - 1) / kTileN;
+    g.tile_start = tiles;
+    g.prob_start = prob;
+    tiles += g.tiles_m * g.tiles_n * g.count;
+    prob += g.count;
+    P.leaf_flops += 2.0 * g.m * g.n * g.k * g.count;
+    P.gemm_min_bytes += (double)es * (g.m * g.k + g.k * g.n + g.m * g.n) * g.count;
+  }
+  P.gemm_tiles = tiles;
+  P.add_bytes = add_bytes;
+  P.ws_bytes = ws.used;
+
+  // Host image of the device descriptor table.
+  Arena tab;
+  P.dev_probs = tab.alloc(sizeof(GemmProb) * P.gemm_probs.size());
+  for (FormPass& fp : P.s_passes) {
+    fp.dev_groups = tab.alloc(sizeof(Ref) * fp.groups.size());
+    fp.dev_outs = tab.alloc(sizeof(int64_t) * fp.outs.size());
+  }
+  for (FormPass& fp : P.t_passes) {
+    fp.dev_groups = tab.alloc(sizeof(Ref) * fp.groups.size());
+    fp.dev_outs = tab.alloc(sizeof(int64_t) * fp.outs.size());
+  }
+  for (CombinePass& cp : P.w_passes) {
+    cp.dev_in = tab.alloc(sizeof(int64_t) * cp.in_off.size());
+    cp.dev_out = tab.alloc(sizeof(Ref) * cp.out.size());
+  }
+  P.table_bytes = tab.used ? tab.used : 256;
+  P.table.assign(P.table_bytes, 0);
+  auto put = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(P.table.data() + off, src, bytes);
+  };
+  put(P.dev_probs, P.gemm_probs.data(), sizeof(GemmProb) * P.gemm_probs.size());
+  for (FormPass& fp : P.s_passes) {
+    put(fp.dev_groups, fp.groups.data(), sizeof(Ref) * fp.groups.size());
+    put(fp.dev_outs, fp.outs.data(), sizeof(int64_t) * fp.outs.size());
+  }
+  for (FormPass& fp : P.t_passes) {
+    put(fp.dev_groups, fp.groups.data(), sizeof(Ref) * fp.groups.size());
+    put(fp.dev_outs, fp.outs.data(), sizeof(int64_t) * fp.outs.size());
+  }
+  for (CombinePass& cp : P.w_passes) {
+    put(cp.dev_in, cp.in_off.data(), sizeof(int64_t) * cp.in_off.size());
+    put(cp.dev_out, cp.out.data(), sizeof(Ref) * cp.out.size());
+  }
+  *code = 0;
+  return std::string();
+}
+
+}  // namespace fmm

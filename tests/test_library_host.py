@@ -1,0 +1,170 @@
+"""Host-side checks of the C-ABI library: exports, compiled-in tables, planner.
+
+No GPU needed: these call only entry points that do not touch a device
+(fmm_plan_host, fmm_plan_info, fmm_plan_operand, the table queries).
+"""
+import ctypes
+import math
+import re
+
+import numpy as np
+import pytest
+
+import paper_1409_2908_amd as F
+from oracle import algorithms, tensor
+from conftest import ROOT
+
+ALGS = ["strassen_222_7", "fmm_333_23", "fmm_323_15", "fmm_423_20", "fmm_424_26", "classical_222_8"]
+
+
+def test_library_exports_every_declared_symbol():
+    with open(f"{ROOT}/include/fmm.h") as f:
+        text = f.read()
+    names = set(re.findall(r"\b(fmm_[a-z0-9_]+)\s*\(", text))
+    assert len(names) >= 15
+    lib = ctypes.CDLL(F.library_path())
+    for nm in sorted(names):
+        assert hasattr(lib, nm), nm
+
+
+@pytest.mark.parametrize("name", ALGS)
+def test_compiled_tables_pass_brent_and_match_oracle_copy(name):
+    M, K, N, R, U, V, W = F.algorithm_coeffs(name)
+    assert tensor.brent_residual(U.tolist(), V.tolist(), W.tolist(), M, K, N) == []
+    a = algorithms.get(name)
+    assert (M, K, N, R) == (a.M, a.K, a.N, a.R)
+    assert U.tolist() == [list(r) for r in a.U]
+    assert V.tolist() == [list(r) for r in a.V]
+    assert W.tolist() == [list(r) for r in a.W]
+
+
+def test_library_brent_self_check():
+    F.check_algorithms()
+
+
+def test_unknown_algorithm_and_bad_args():
+    with pytest.raises(F.FmmError) as e:
+        F.Plan("no_such_alg", 8, 8, 8, 1, host_only=True)
+    assert e.value.code == 5
+    with pytest.raises(F.FmmError) as e:
+        F.Plan("strassen_222_7", -1, 8, 8, 1, host_only=True)
+    assert e.value.code == 1
+    # depth leaves a leaf dimension < 1
+    with pytest.raises(F.FmmError) as e:
+        F.Plan("strassen_222_7", 7, 64, 64, 3, host_only=True)
+    assert e.value.code == 1
+    with pytest.raises(F.FmmError):
+        F.Plan("strassen_222_7", 8, 8, 8, 1, dtype=7, host_only=True)
+
+
+def _ipow(b, e):
+    return b ** e
+
+
+@pytest.mark.parametrize("name,L,shape", [
+    ("strassen_222_7", 1, (512, 512, 512)),
+    ("strassen_222_7", 3, (9000, 9000, 9000)),
+    ("fmm_424_26", 2, (9000, 9000, 9000)),
+    ("fmm_423_20", 2, (16384, 16384, 2400)),
+    ("fmm_333_23", 2, (4097, 1001, 30)),
+    ("fmm_323_15", 1, (3, 2, 3)),
+    ("fmm_424_26", 1, (5, 3, 9)),
+])
+def test_planner_peel_and_leaves(name, L, shape):
+    m, k, n = shape
+    a = algorithms.get(name)
+    p = F.Plan(name, m, k, n, L, host_only=True)
+    i = p.info
+    fm, fk, fn = a.M ** L, a.K ** L, a.N ** L
+    assert (i["m0"], i["k0"], i["n0"]) == (m // fm * fm, k // fk * fk, n // fn * fn)
+    assert (i["leaf_m"], i["leaf_k"], i["leaf_n"]) == (m // fm, k // fk, n // fn)
+    assert i["num_leaves"] == a.R ** L
+    peels = (i["k0"] < k) + (i["n0"] < n) + (i["m0"] < m)
+    assert i["num_gemm_problems"] == a.R ** L + peels
+    # leaf flops: R^L leaf products plus the classical peel products
+    lm, lk, ln = i["leaf_m"], i["leaf_k"], i["leaf_n"]
+    m0, k0, n0 = i["m0"], i["k0"], i["n0"]
+    expect = 2 * lm * lk * ln * a.R ** L + 2 * m0 * (k - k0) * n0 + 2 * m0 * k * (n - n0) \
+        + 2 * (m - m0) * k * n
+    assert i["leaf_flops"] == pytest.approx(expect, rel=1e-12)
+    assert i["classical_flops"] == 2.0 * m * k * n
+
+
+def _single(X, r):
+    return sum(1 for v in X[:, r] if v) == 1
+
+
+@pytest.mark.parametrize("name", ["strassen_222_7", "fmm_333_23", "fmm_424_26"])
+@pytest.mark.parametrize("L", [1, 2])
+@pytest.mark.parametrize("fuse", ["1", "2"])
+def test_single_nonzero_columns_become_views(name, L, fuse, monkeypatch):
+    """Leaf operands whose U (V) columns have one non-zero at every level are
+    scaled views of A (B) (Section 3.1: no temporary for such columns).  With
+    all levels formed in one pass every other leaf operand is written to the
+    workspace; with one level per pass, an operand whose deeper levels are
+    single-non-zero is a scaled view of an intermediate instead."""
+    monkeypatch.setenv("FMM_FUSE", fuse)
+    M, K, N, R, U, V, W = F.algorithm_coeffs(name)
+    p = F.Plan(name, M ** L * 8, K ** L * 8, N ** L * 8, L, host_only=True)
+    info = p.info
+    for side, X, loc_in in ((0, U, F.LOC_A), (1, V, F.LOC_B)):
+        views = ws_views = 0
+        for leaf in range(R ** L):
+            digits = [(leaf // R ** (L - 1 - j)) % R for j in range(L)]
+            loc, off, row, col, ld, alpha = p.operand(side, leaf)
+            if all(_single(X, d) for d in digits):
+                assert loc == loc_in
+                views += 1
+                coef = np.prod([X[:, d][X[:, d] != 0][0] for d in digits])
+                assert alpha == coef
+            else:
+                assert loc == F.LOC_WORKSPACE
+                if L == 2 and fuse == "1" and _single(X, digits[1]):
+                    ws_views += 1
+                    assert alpha == X[:, digits[1]][X[:, digits[1]] != 0][0]
+                else:
+                    assert alpha == 1.0
+        nmat = info["num_s_materialized"] if side == 0 else info["num_t_materialized"]
+        assert nmat == R ** L - views - ws_views
+    for leaf in range(R ** L):
+        assert p.operand(2, leaf)[0] == F.LOC_WORKSPACE
+
+
+def test_strassen_view_positions():
+    """S_3 = A11 and S_4 = A22 (Section 2.1) are views at the right blocks."""
+    p = F.Plan("strassen_222_7", 64, 64, 64, 1, host_only=True)
+    assert p.operand(0, 2)[:4] == (F.LOC_A, 0, 0, 0)
+    assert p.operand(0, 3)[:4] == (F.LOC_A, 0, 32, 32)
+    # T_2 = B11, T_5 = B22
+    assert p.operand(1, 1)[:4] == (F.LOC_B, 0, 0, 0)
+    assert p.operand(1, 4)[:4] == (F.LOC_B, 0, 32, 32)
+
+
+def test_workspace_and_addition_bytes_model():
+    """Strassen, one level, 512^3 FP64: five S and five T blocks of 256x256 are
+    written (two columns of U and of V have one non-zero), seven products of
+    256x256; the streaming byte count is reads of A, B and the 7 products plus
+    writes of the 10 formed operands and of C."""
+    p = F.Plan("strassen_222_7", 512, 512, 512, 1, host_only=True)
+    i = p.info
+    blk = 256 * 256 * 8
+    assert i["num_s_materialized"] == 5 and i["num_t_materialized"] == 5
+    assert i["workspace_bytes"] >= (5 + 5 + 7) * blk
+    assert i["workspace_bytes"] < (5 + 5 + 7) * blk + 64 * 1024
+    reads = 4 * blk + 4 * blk + 7 * blk
+    writes = 5 * blk + 5 * blk + 4 * blk
+    assert i["add_bytes"] == reads + writes
+
+
+def test_zero_sizes_are_valid():
+    for (m, k, n) in [(0, 5, 5), (5, 0, 5), (5, 5, 0), (0, 0, 0)]:
+        p = F.Plan("strassen_222_7", m, k, n, 2, host_only=True)
+        assert p.info["levels"] == 0
+
+
+def test_host_only_plan_cannot_run():
+    p = F.Plan("strassen_222_7", 64, 64, 64, 1, host_only=True)
+    lib = ctypes.CDLL(F.library_path())
+    lib.fmm_multiply.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p, ctypes.c_int64] * 3 + [ctypes.c_void_p]
+    lib.fmm_multiply.restype = ctypes.c_int
+    assert lib.fmm_multiply(p._p, 1, 64, 2, 64, 3, 64, None) == 1
