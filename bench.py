@@ -1,0 +1,178 @@
+"""Benchmark: recursive fast matrix multiplication on one MI355X.
+
+One step = one fmm_multiply over the whole hot path (operand formation, the
+grouped leaf GEMM launch, the W-combination) of a synthetic FP64 square
+product with inputs resident in HBM.  Default workload: 16384^3 FP64,
+uniform[-1,1) operands, the base case and depth given by --alg/--levels.
+
+Prints one JSON line with the effective rate 2mkn/t, the same-GPU classical
+GEMM rate, the leaf GEMM's roofline figures (live HIP events on the launch
+stream), the error on sampled rows against the CPU oracle, and the oracle's
+own rate on those rows as the CPU baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def traffic_from_profile(kernel_tag):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if
+    its kernel source hash matches the current source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        import hashlib
+        src = os.path.join(ROOT, rec["source"])
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if h != rec.get("source_sha256"):
+            return None
+        return rec.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=16384, help="m = k = n")
+    ap.add_argument("--alg", default="strassen_222_7")
+    ap.add_argument("--levels", type=int, default=2)
+    ap.add_argument("--dtype", default="f64", choices=["f64"])
+    ap.add_argument("--cpu-rows", type=int, default=32, help="rows of the oracle CPU baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on exactly one GPU; the fast-multiplication hot path is "
+              "measured per GPU (--gpus 1).  Multi-GPU sharding is design-only.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import fmm_inputs
+    import paper_1409_2908_amd as F
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = args.n
+    m = k = n
+    log(f"[bench] generating {m}x{k} and {k}x{n} FP64 operands")
+    A, B = fmm_inputs.operands(0, m, k, n, "uniform")
+    dA = torch.from_numpy(A).to(dev)
+    dB = torch.from_numpy(B).to(dev)
+    dC = torch.empty((m, n), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    plan = F.Plan(args.alg, m, k, n, args.levels, F.F64)
+    info = plan.info
+    log(f"[bench] plan {args.alg} L={args.levels}: leaf {info['leaf_m']}x{info['leaf_k']}x{info['leaf_n']}"
+        f" x{info['num_leaves']}, workspace {info['workspace_bytes'] / 2**30:.2f} GiB")
+
+    for _ in range(args.warmup):
+        plan.multiply(dA, dB, dC)
+    torch.cuda.synchronize()
+
+    plan.enable_timing(max(args.steps, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.multiply(dA, dB, dC)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stage_ms = plan.stage_ms()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    eff_tflops = 2.0 * m * k * n / (ms_per_step * 1e-3) / 1e12
+    log(f"[bench] fast: {ms_per_step:.3f} ms/step, {eff_tflops:.2f} effective TFLOP/s, stages {stage_ms}")
+
+    # same-GPU classical baseline: the same MFMA kernel on the one full problem
+    for _ in range(2):
+        F.gemm(dA, dB, dC)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    csteps = max(3, min(args.steps, 5))
+    ev0.record(stream)
+    for _ in range(csteps):
+        F.gemm(dA, dB, dC)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    classical_ms = ev0.elapsed_time(ev1) / csteps
+    classical_tflops = 2.0 * m * k * n / (classical_ms * 1e-3) / 1e12
+    log(f"[bench] classical MFMA GEMM: {classical_ms:.3f} ms, {classical_tflops:.2f} TFLOP/s")
+
+    # error on sampled rows + CPU baseline (the oracle on those rows)
+    plan.multiply(dA, dB, dC)
+    torch.cuda.synchronize()
+    err = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import classical as oracle_classical
+        a = F.algorithm_coeffs(args.alg) if args.alg != "classical" else (1, 1, 1)
+        h = m // (a[0] ** args.levels)
+        must = [0, m - 1] + [b * h for b in range(a[0] ** args.levels)]
+        rows = fmm_inputs.sample_rows(1, m, args.cpu_rows, must)
+        got = dC[torch.from_numpy(rows).to(dev)].cpu().numpy()
+        tc0 = time.perf_counter()
+        ref = oracle_classical.gemm_rows(A, B, rows)
+        tc1 = time.perf_counter()
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        cpu_flops = 2.0 * len(rows) * k * n
+        cpu = {"value": cpu_flops / (tc1 - tc0) / 1e12, "unit": "TFLOP/s",
+               "cores": oracle_classical.num_threads(), "kind": "oracle",
+               "sample": f"{len(rows)} rows of the {m}x{k}x{n} product ({cpu_flops / 1e9:.1f} GFLOP, "
+                         f"{tc1 - tc0:.1f} s)"}
+        log(f"[bench] sampled-row relF {err:.3e}; oracle {cpu['value'] * 1e3:.2f} GFLOP/s on {cpu['cores']} threads")
+
+    leaf_ms = stage_ms[F.STAGE_LEAF]
+    leaf_tflops = info["leaf_flops"] / (leaf_ms * 1e-3) / 1e12
+    traffic = traffic_from_profile("gemm_f64")
+    out = {
+        "metric": "effective TFLOP/s (2mkn/t) vs classical GEMM at fixed error; p50/p99 latency",
+        "value": round(eff_tflops, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"FP64 square {m}x{k}x{n}, uniform[-1,1), {args.alg} at {args.levels} levels",
+                   "m": m, "k": k, "n": n, "alg": args.alg, "levels": args.levels},
+        "classical_same_gpu_tflops": round(classical_tflops, 3),
+        "speedup_vs_classical": round(eff_tflops / classical_tflops, 4),
+        "error_relF_sampled_rows": err,
+        "stage_ms": {"form_s": stage_ms[0], "form_t": stage_ms[1], "leaf_gemm": stage_ms[2],
+                     "combine": stage_ms[3]},
+        "roofline": {"bound": "mfma", "kernel": "gemm_kernel<double>",
+                     "achieved": round(leaf_tflops, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(leaf_tflops / FP64_PEAK_TFLOPS, 4), "traffic": traffic},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -133,10 +133,13 @@ void *fmm_plan_workspace(fmm_plan_t p);
 size_t fmm_plan_workspace_bytes(fmm_plan_t p);
 fmm_status fmm_plan_info(fmm_plan_t p, fmm_plan_info_t *info);
 
-/* Stage timing: when enabled, every later fmm_multiply records HIP events on
- * its stream around each stage; fmm_plan_stage_ms waits for the last multiply
- * and returns the four stage durations in milliseconds. */
-fmm_status fmm_plan_enable_timing(fmm_plan_t p, int enable);
+/* Stage timing.  fmm_plan_enable_timing(p, slots) with slots > 0 creates
+ * (slots * 5) HIP events once; every later fmm_multiply on p records one event
+ * before each stage and one after the last, on its own stream, into a ring of
+ * `slots` multiplies (slots = 0 turns recording off).  fmm_plan_stage_ms waits
+ * for the recorded multiplies and writes the mean duration of each stage, in
+ * milliseconds, over the most recent min(timed, slots) of them. */
+fmm_status fmm_plan_enable_timing(fmm_plan_t p, int slots);
 fmm_status fmm_plan_stage_ms(fmm_plan_t p, double ms[FMM_NUM_STAGES]);
 
 /* Frees the workspace and tables.  NULL is accepted. */

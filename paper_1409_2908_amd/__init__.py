@@ -185,8 +185,9 @@ class Plan:
                                      ctypes.byref(alpha)))
         return loc.value, off.value, row.value, col.value, ld.value, alpha.value
 
-    def enable_timing(self, on=True):
-        _check(_lib.fmm_plan_enable_timing(self._p, 1 if on else 0))
+    def enable_timing(self, slots=64):
+        """Record per-stage HIP events for the next multiplies (ring of `slots`)."""
+        _check(_lib.fmm_plan_enable_timing(self._p, int(slots)))
 
     def stage_ms(self):
         out = (ctypes.c_double * 4)()

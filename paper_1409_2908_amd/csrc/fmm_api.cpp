@@ -293,51 +293,58 @@ fmm_status fmm_multiply(fmm_plan_t p, const void* A, int64_t lda, const void* B,
   if (cur != P.device) return fail(FMM_EINVAL, "plan belongs to another device");
   const fmm::Bases b = make_bases(P, A, lda, B, ldb, C, ldc);
   hipStream_t s = (hipStream_t)stream;
+  const size_t slot = P.timing_slots ? (size_t)(P.timed % P.timing_slots) * (FMM_NUM_STAGES + 1) : 0;
   for (int stage = 0; stage < FMM_NUM_STAGES; ++stage) {
-    if (P.timing) {
-      hipError_t e = hipEventRecord((hipEvent_t)P.events[stage], s);
+    if (P.timing_slots) {
+      hipError_t e = hipEventRecord((hipEvent_t)P.events[slot + stage], s);
       if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
     hipError_t e = run_stage(P, stage, b, s);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
   }
-  if (P.timing) {
-    hipError_t e = hipEventRecord((hipEvent_t)P.events[FMM_NUM_STAGES], s);
+  if (P.timing_slots) {
+    hipError_t e = hipEventRecord((hipEvent_t)P.events[slot + FMM_NUM_STAGES], s);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    P.timed_once = true;
+    ++P.timed;
   }
   return FMM_OK;
 }
 
-fmm_status fmm_plan_enable_timing(fmm_plan_t p, int enable) {
+fmm_status fmm_plan_enable_timing(fmm_plan_t p, int slots) {
   if (!p) return fail(FMM_EINVAL, "plan is NULL");
   fmm::Plan& P = p->P;
   if (P.host_only) return fail(FMM_EINVAL, "host-only plan");
-  if (enable && !P.events[0]) {
-    for (int i = 0; i <= FMM_NUM_STAGES; ++i) {
-      hipEvent_t ev;
-      hipError_t e = hipEventCreate(&ev);
-      if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-      P.events[i] = ev;
-    }
+  if (slots < 0) return fail(FMM_EINVAL, "slots must be >= 0");
+  const size_t need = (size_t)slots * (FMM_NUM_STAGES + 1);
+  while (P.events.size() < need) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    P.events.push_back(ev);
   }
-  P.timing = enable != 0;
-  P.timed_once = false;
+  P.timing_slots = slots;
+  P.timed = 0;
   return FMM_OK;
 }
 
 fmm_status fmm_plan_stage_ms(fmm_plan_t p, double ms[FMM_NUM_STAGES]) {
   if (!p || !ms) return fail(FMM_EINVAL, "NULL argument");
   fmm::Plan& P = p->P;
-  if (!P.timed_once) return fail(FMM_EINVAL, "no timed multiply yet");
-  hipError_t e = hipEventSynchronize((hipEvent_t)P.events[FMM_NUM_STAGES]);
-  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-  for (int i = 0; i < FMM_NUM_STAGES; ++i) {
-    float f = 0;
-    e = hipEventElapsedTime(&f, (hipEvent_t)P.events[i], (hipEvent_t)P.events[i + 1]);
-    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
-    ms[i] = f;
+  if (!P.timing_slots || P.timed == 0) return fail(FMM_EINVAL, "no timed multiply yet");
+  const int64_t n = P.timed < P.timing_slots ? P.timed : P.timing_slots;
+  for (int i = 0; i < FMM_NUM_STAGES; ++i) ms[i] = 0;
+  for (int64_t t = P.timed - n; t < P.timed; ++t) {
+    const size_t slot = (size_t)(t % P.timing_slots) * (FMM_NUM_STAGES + 1);
+    hipError_t e = hipEventSynchronize((hipEvent_t)P.events[slot + FMM_NUM_STAGES]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    for (int i = 0; i < FMM_NUM_STAGES; ++i) {
+      float f = 0;
+      e = hipEventElapsedTime(&f, (hipEvent_t)P.events[slot + i], (hipEvent_t)P.events[slot + i + 1]);
+      if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+      ms[i] += f;
+    }
   }
+  for (int i = 0; i < FMM_NUM_STAGES; ++i) ms[i] /= (double)n;
   return FMM_OK;
 }
 
@@ -405,8 +412,7 @@ fmm_status fmm_plan_destroy(fmm_plan_t p) {
     if (prev != P.device) (void)hipSetDevice(P.device);
     if (P.ws && hipFree(P.ws) != hipSuccess) st = fail(FMM_EHIP, "hipFree of the workspace failed");
     if (P.dev_table && hipFree(P.dev_table) != hipSuccess) st = fail(FMM_EHIP, "hipFree of the table failed");
-    for (void* ev : P.events)
-      if (ev) (void)hipEventDestroy((hipEvent_t)ev);
+    for (void* ev : P.events) (void)hipEventDestroy((hipEvent_t)ev);
     if (prev != P.device && prev >= 0) (void)hipSetDevice(prev);
   }
   delete p;

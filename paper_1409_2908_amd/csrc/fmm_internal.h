@@ -155,9 +155,9 @@ struct Plan {
   int device = -1;
   void* ws = nullptr;
   void* dev_table = nullptr;
-  bool timing = false;
-  void* events[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  bool timed_once = false;
+  int timing_slots = 0;         // 0: timing off; else ring of this many multiplies
+  std::vector<void*> events;    // (stages + 1) HIP events per slot
+  int64_t timed = 0;            // timed multiplies since timing was enabled
 
   double leaf_flops = 0, add_bytes = 0, gemm_min_bytes = 0;
 };
