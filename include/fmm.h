@@ -20,6 +20,8 @@
  *  - Errors are reported by status code; no C++ exception crosses the ABI.
  *    fmm_last_error() returns a message for the calling thread's last error.
  *  - A size of zero (m, k or n) is a valid no-op (with k == 0, C is zeroed).
+ *  - Leading dimensions must be below 2^21 elements (FMM_EUNSUPPORTED otherwise):
+ *    the leaf kernels address a 128-row tile with 32-bit byte offsets.
  */
 #ifndef FMM_H
 #define FMM_H

@@ -79,6 +79,8 @@ fmm_status check_tables_once() {
 
 size_t elt_size(int elt) { return elt == fmm::ELT_F64 ? 8 : 4; }
 
+constexpr int64_t kMaxLd = (int64_t)1 << 21;
+
 bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
   const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
   return abytes && bbytes && x < y + bbytes && y < x + abytes;
@@ -94,6 +96,9 @@ fmm_status validate(const fmm::Plan& P, const void* A, int64_t lda, const void* 
   if (P.m == 0 || P.n == 0) return FMM_OK;
   if (!C) return fail(FMM_EINVAL, "C is NULL");
   if (ldc < P.n) return fail(FMM_EINVAL, "ldc < n");
+  // The leaf kernels address a 128-row tile with 32-bit byte offsets.
+  if (lda >= kMaxLd || ldb >= kMaxLd || ldc >= kMaxLd)
+    return fail(FMM_EUNSUPPORTED, "leading dimensions must be below 2^21 elements");
   if (P.k > 0) {
     if (!A || !B) return fail(FMM_EINVAL, "A or B is NULL");
     if (lda < P.k) return fail(FMM_EINVAL, "lda < k");

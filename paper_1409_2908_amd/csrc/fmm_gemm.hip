@@ -8,14 +8,23 @@
 // static stride, so there is no per-problem launch and no load imbalance
 // beyond one tile.
 //
-// Tile: 128 x 128 per workgroup of 8 wavefronts (4 x 2), 32 x 64 per
-// wavefront = 2 x 4 MFMA 16x16x4 blocks (64 FP64 accumulator values per lane,
-// so two wavefronts fit each SIMD without spilling).  K advances 16 at a time through a
-// double-buffered LDS stage: global loads for step k+1 are issued before the
-// MFMAs of step k, stored to the other LDS buffer after them, one barrier per
-// step.  Within a K step lane group g of a wavefront supplies k = 4g + kk for
-// MFMA kk (any bijection of k works when A and B use the same one), so each
-// lane reads its A fragment from one LDS row.
+// Tile: 128 x 128 per workgroup of 4 wavefronts (2 x 2), 64 x 64 per
+// wavefront = 4 x 4 MFMA 16x16x4 blocks.  Two workgroups share each compute
+// unit (so each SIMD runs two wavefronts of different workgroups, whose
+// barriers do not line up and keep the matrix pipe fed).  K advances 16 at a
+// time through a double-buffered LDS stage: global loads for step k+1 are
+// issued before the MFMAs of step k and stored to the other LDS buffer after
+// them, one barrier per step.  Within a K step lane group g of a wavefront
+// supplies k = 4g + kk for MFMA kk (any bijection of k works when A and B use
+// the same one), so each lane reads its A fragment from one LDS row.
+//
+// Operands are read and C is written with raw buffer instructions: a
+// per-step 128-bit resource in scalar registers plus one 32-bit byte offset
+// per element, so a lane needs no 64-bit address.  Out-of-range elements
+// (tile edges, the K tail) get an offset past the resource's size: the
+// hardware returns 0 for such loads and drops such stores, so edges need no
+// branches.  This bounds each operand row offset: ld * 128 * 8 bytes must
+// stay below 2^31 (the host rejects larger leading dimensions).
 //
 // Order: consecutive workgroup ids are dispatched round-robin over the 8 XCDs,
 // each with its own L2; workgroup b is given flat slot (b mod 8) * (G/8) + b/8
@@ -30,8 +39,33 @@ namespace fmm {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef unsigned u2_t __attribute__((ext_vector_type(2)));
 
-constexpr int GBM = 128, GBN = 128, GBK = 16, GNT = 512;
+constexpr int GBM = 128, GBN = 128, GBK = 16, GNT = 256;
+constexpr int kInvalidOff = (int)0x80000000;  // beyond kNumRecords: loads read 0, stores drop
+constexpr int kNumRecords = 0x7ffffff0;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p) {
+  // 0x00020000: 32-bit data format word of a raw (unformatted) gfx9 buffer
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, kNumRecords, 0x00020000);
+}
+
+__device__ __forceinline__ int uniform_int(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ double uniform_double(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <typename P>
+__device__ __forceinline__ P* uniform_ptr(P* p) {
+  const unsigned long long u = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return (P*)(((unsigned long long)hi << 32) | lo);
+}
 
 template <typename T>
 struct Mfma;
@@ -45,6 +79,12 @@ struct Mfma<double> {
   }
   // output row of register v in lane l (16x16 block; column is l % 16)
   static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+  static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, int off, int soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
+  }
+  static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int off, double x) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, x), r, off, 0, 0);
+  }
 };
 
 template <>
@@ -55,6 +95,12 @@ struct Mfma<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+  static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, int off, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+  }
+  static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int off, float x) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, off, 0, 0);
+  }
 };
 
 struct TileJob {
@@ -95,16 +141,23 @@ __device__ __forceinline__ TileJob decode_tile(const GemmArgs& args, int64_t t) 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(GNT) gemm_kernel(GemmArgs args) {
+__global__ void __launch_bounds__(GNT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+gemm_kernel(GemmArgs args) {
   using MF = Mfma<T>;
   using acc_t = typename MF::acc_t;
+  constexpr int ES = (int)sizeof(T);
+  constexpr int WTM = 64, WTN = 64, TI = 4, TJ = 4;
+  constexpr int EA = GBM * GBK / GNT, EB = GBK * GBN / GNT;  // 8 and 8 elements per thread
+  constexpr int RA = GNT / GBK, RB = GNT / GBN;                // rows per load step: 16 and 2
+  constexpr int KPL = GBK / 4;                                 // k per lane group per step
   __shared__ T As[2][GBM][GBK + MF::APAD];
   __shared__ T Bs[2][GBK][GBN + MF::BPAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;  // 4 x 2 wavefronts
+  const int wm = wave >> 1, wn = wave & 1;
   const int li = lane & 15, lg = lane >> 4;
+  const int ar = tid / GBK, ac = tid % GBK, br = tid / GBN, bc = tid % GBN;
   const int64_t G = gridDim.x;
   const int64_t slot = (int64_t)(blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
 
@@ -115,38 +168,51 @@ __global__ void __launch_bounds__(GNT) gemm_kernel(GemmArgs args) {
     const T* A = (const T*)buf_ptr(args.bases, pr.a, &lda) + pr.a.off;
     const T* B = (const T*)buf_ptr(args.bases, pr.b, &ldb) + pr.b.off;
     T* C = (T*)buf_ptr(args.bases, pr.c, &ldc) + pr.c.off;
-    A += (pr.a.row + job.tm * GBM) * lda + pr.a.col;
-    B += pr.b.row * ldb + pr.b.col + job.tn * GBN;
-    C += (pr.c.row + job.tm * GBM) * ldc + pr.c.col + job.tn * GBN;
-    const int64_t mrem = job.m - job.tm * GBM;
-    const int64_t nrem = job.n - job.tn * GBN;
+    // Everything below is the same for the whole workgroup; saying so keeps
+    // the buffer resources in scalar registers.
+    A = uniform_ptr(A + (pr.a.row + job.tm * GBM) * lda + pr.a.col);
+    B = uniform_ptr(B + pr.b.row * ldb + pr.b.col + job.tn * GBN);
+    C = uniform_ptr(C + (pr.c.row + job.tm * GBM) * ldc + pr.c.col + job.tn * GBN);
+    const int64_t mr = job.m - job.tm * GBM, nr = job.n - job.tn * GBN;
+    const int mrem = uniform_int(mr < GBM ? (int)mr : GBM);
+    const int nrem = uniform_int(nr < GBN ? (int)nr : GBN);
     const int64_t K = job.k;
+    const int ilda = uniform_int((int)lda), ildb = uniform_int((int)ldb), ildc = uniform_int((int)ldc);
+    const T alpha = (T)uniform_double(pr.alpha);
 
-    acc_t acc[2][4];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+    // One byte offset per operand and lane; the EA (EB) rows a lane loads are
+    // RA (RB) rows apart, a stride passed as the scalar offset.  Lanes past the
+    // tile's last row or column (or past K) load through kInvalidOff and read 0.
+    const int a_base = (ar * ilda + ac) * ES;
+    const int a_rows = (mrem - ar + RA - 1) / RA;  // valid rows of this lane
+    const int b_base = bc < nrem ? (br * ildb + bc) * ES : kInvalidOff;
+    const int a_step = uniform_int(RA * ilda * ES), b_step = uniform_int(RB * ildb * ES);
 
-    // Each thread moves 4 elements of the A tile and 4 of the B tile per K
-    // step; 16 (A) or 128 (B) consecutive threads cover one contiguous row.
-    T ra[4], rb[4];
-    const int ar = tid >> 4, ac = tid & 15, br = tid >> 7, bc = tid & 127;
+    acc_t acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+    T ra[EA], rb[EB];
     auto gload = [&](int64_t k0) {
+      const __amdgpu_buffer_rsrc_t sa = make_rsrc(A + k0);
+      const __amdgpu_buffer_rsrc_t sb = make_rsrc(B + k0 * (int64_t)ildb);
+      // One branch-free path for full and partial K steps: a branch here would
+      // merge the loaded registers and force a wait for the loads to land.
+      const int kr = K - k0 < GBK ? (int)(K - k0) : GBK;
+      const int av = ac < kr ? a_base : kInvalidOff;
+      const int b_rows = (kr - br + RB - 1) / RB;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = ar + 32 * j;
-        ra[j] = (r < mrem && k0 + ac < K) ? A[r * lda + k0 + ac] : T(0);
-        const int kr = br + 4 * j;
-        rb[j] = (k0 + kr < K && bc < nrem) ? B[(k0 + kr) * ldb + bc] : T(0);
-      }
+      for (int j = 0; j < EA; ++j) ra[j] = MF::load(sa, j < a_rows ? av : kInvalidOff, j * a_step);
+#pragma unroll
+      for (int j = 0; j < EB; ++j) rb[j] = MF::load(sb, j < b_rows ? b_base : kInvalidOff, j * b_step);
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        As[buf][ar + 32 * j][ac] = ra[j];
-        Bs[buf][br + 4 * j][bc] = rb[j];
-      }
+      for (int j = 0; j < EA; ++j) As[buf][ar + RA * j][ac] = ra[j];
+#pragma unroll
+      for (int j = 0; j < EB; ++j) Bs[buf][br + RB * j][bc] = rb[j];
     };
 
     const int64_t nk = (K + GBK - 1) / GBK;
@@ -159,31 +225,31 @@ __global__ void __launch_bounds__(GNT) gemm_kernel(GemmArgs args) {
       const int cur = (int)(kt & 1);
       if (kt + 1 < nk) gload((kt + 1) * GBK);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        T af[2], bf[4];
+      for (int kk = 0; kk < KPL; ++kk) {
+        T af[TI], bf[TJ];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) af[i] = As[cur][wm * 32 + i * 16 + li][lg * 4 + kk];
+        for (int i = 0; i < TI; ++i) af[i] = As[cur][wm * WTM + i * 16 + li][lg * KPL + kk];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bf[j] = Bs[cur][lg * 4 + kk][wn * 64 + j * 16 + li];
+        for (int j = 0; j < TJ; ++j) bf[j] = Bs[cur][lg * KPL + kk][wn * WTN + j * 16 + li];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < TI; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = MF::op(af[i], bf[j], acc[i][j]);
+          for (int j = 0; j < TJ; ++j) acc[i][j] = MF::op(af[i], bf[j], acc[i][j]);
       }
       if (kt + 1 < nk) lstore(cur ^ 1);
       __syncthreads();
     }
 
-    const T alpha = (T)pr.alpha;
+    const __amdgpu_buffer_rsrc_t sc = make_rsrc(C);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < TJ; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int r = wm * 32 + i * 16 + MF::row(lane, v);
-          const int c = wn * 64 + j * 16 + li;
-          if (r < mrem && c < nrem) C[r * ldc + c] = alpha * acc[i][j][v];
+          const int r = wm * WTM + i * 16 + MF::row(lane, v);
+          const int c = wn * WTN + j * 16 + li;
+          MF::store(sc, (r < mrem && c < nrem) ? (r * ildc + c) * ES : kInvalidOff, alpha * acc[i][j][v]);
         }
   }
 }
