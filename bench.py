@@ -55,8 +55,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=16384, help="m = k = n")
-    ap.add_argument("--alg", default="strassen_222_7")
+    ap.add_argument("--alg", default="fmm_424_26")
     ap.add_argument("--levels", type=int, default=2)
+    ap.add_argument("--fuse", type=int, default=0, help="levels per addition pass (0 = library default)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a 1 GiB device copy first (reference dispatch for HBM counters)")
     ap.add_argument("--dtype", default="f64", choices=["f64"])
     ap.add_argument("--cpu-rows", type=int, default=32, help="rows of the oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -83,7 +86,15 @@ def main():
     dC = torch.empty((m, n), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
-    plan = F.Plan(args.alg, m, k, n, args.levels, F.F64)
+    if args.calibrate_copy:
+        # a plain copy of exactly 2^30 bytes: reads 1 GiB, writes 1 GiB
+        src = torch.ones(2 ** 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    plan = F.Plan(args.alg, m, k, n, args.levels, F.F64, fuse_levels=args.fuse)
     info = plan.info
     log(f"[bench] plan {args.alg} L={args.levels}: leaf {info['leaf_m']}x{info['leaf_k']}x{info['leaf_n']}"
         f" x{info['num_leaves']}, workspace {info['workspace_bytes'] / 2**30:.2f} GiB")
@@ -159,7 +170,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"FP64 square {m}x{k}x{n}, uniform[-1,1), {args.alg} at {args.levels} levels",
-                   "m": m, "k": k, "n": n, "alg": args.alg, "levels": args.levels},
+                   "m": m, "k": k, "n": n, "alg": args.alg, "levels": args.levels,
+                   "fuse_levels": info["fuse_levels"]},
         "classical_same_gpu_tflops": round(classical_tflops, 3),
         "speedup_vs_classical": round(eff_tflops / classical_tflops, 4),
         "error_relF_sampled_rows": err,

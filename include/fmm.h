@@ -82,7 +82,15 @@ typedef struct {
     double classical_flops;      /* 2 m k n, the effective-flop numerator */
     double add_bytes;            /* algorithmic bytes moved by the S, T and W stages */
     double gemm_min_bytes;       /* bytes the leaf stage must read and write at least once */
+    int fuse_levels;             /* recursion levels formed / combined per addition pass */
 } fmm_plan_info_t;
+
+/* Options of fmm_plan_ex.  Zero-initialise, then set what you need. */
+typedef struct {
+    int fuse_levels;   /* 0: library default (2 for base cases with R <= 8, else 1);
+                          1 or 2: recursion levels per operand-formation / combination pass */
+    int host_only;     /* non-zero: plan on the host only, as fmm_plan_host */
+} fmm_plan_options_t;
 
 /* Plan C = A*B for an m x k by k x n product with `levels` recursive steps of
  * the base case `alg` ("classical" for a plain GEMM; "strassen_222_7",
@@ -104,6 +112,14 @@ fmm_status fmm_plan(fmm_plan_t *out, const char *alg, int64_t m, int64_t k, int6
  * fmm_multiply on it returns FMM_EINVAL. */
 fmm_status fmm_plan_host(fmm_plan_t *out, const char *alg, int64_t m, int64_t k, int64_t n,
                          int levels, int dtype);
+
+/* fmm_plan with options (NULL = defaults).  Fusing two levels per addition
+ * pass moves fewer bytes (each leaf operand is written once, with no
+ * intermediate level), at the cost of more output streams per thread.  The
+ * choice changes neither the arithmetic nor its order: results are bitwise
+ * identical for every setting. */
+fmm_status fmm_plan_ex(fmm_plan_t *out, const char *alg, int64_t m, int64_t k, int64_t n,
+                       int levels, int dtype, const fmm_plan_options_t *opts);
 
 /* Enqueue C = A*B on `stream` using plan p.  One multiply may be in flight per
  * plan at a time (the workspace is shared); use one plan per concurrent

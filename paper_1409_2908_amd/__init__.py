@@ -46,7 +46,12 @@ class _Info(ctypes.Structure):
                 ("num_t_materialized", ctypes.c_int64), ("num_gemm_problems", ctypes.c_int64),
                 ("gemm_tiles", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t),
                 ("leaf_flops", ctypes.c_double), ("classical_flops", ctypes.c_double),
-                ("add_bytes", ctypes.c_double), ("gemm_min_bytes", ctypes.c_double)]
+                ("add_bytes", ctypes.c_double), ("gemm_min_bytes", ctypes.c_double),
+                ("fuse_levels", ctypes.c_int)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("fuse_levels", ctypes.c_int), ("host_only", ctypes.c_int)]
 
 
 def _load():
@@ -60,6 +65,8 @@ def _load():
     sig = {
         "fmm_plan": ([ctypes.POINTER(P), ctypes.c_char_p, i64, i64, i64, i32, i32], i32),
         "fmm_plan_host": ([ctypes.POINTER(P), ctypes.c_char_p, i64, i64, i64, i32, i32], i32),
+        "fmm_plan_ex": ([ctypes.POINTER(P), ctypes.c_char_p, i64, i64, i64, i32, i32,
+                         ctypes.POINTER(_Options)], i32),
         "fmm_multiply": ([P, vp, i64, vp, i64, vp, i64, vp], i32),
         "fmm_run_stage": ([P, i32, vp, i64, vp, i64, vp, i64, vp], i32),
         "fmm_plan_operand": ([P, i32, i64, ctypes.POINTER(i32), ctypes.POINTER(i64),
@@ -125,11 +132,12 @@ class Plan:
     """A planned product C = A @ B (``fmm_plan``).  ``host_only`` plans
     (``fmm_plan_host``) can be inspected but not run."""
 
-    def __init__(self, alg, m, k, n, levels, dtype=F64, host_only=False):
+    def __init__(self, alg, m, k, n, levels, dtype=F64, host_only=False, fuse_levels=0):
         self._p = ctypes.c_void_p()
         self.dtype = _dtype_code(dtype)
-        fn = _lib.fmm_plan_host if host_only else _lib.fmm_plan
-        _check(fn(ctypes.byref(self._p), alg.encode(), m, k, n, levels, self.dtype))
+        opts = _Options(int(fuse_levels), 1 if host_only else 0)
+        _check(_lib.fmm_plan_ex(ctypes.byref(self._p), alg.encode(), m, k, n, levels, self.dtype,
+                                ctypes.byref(opts)))
         self.alg, self.m, self.k, self.n, self.levels = alg, m, k, n, levels
         self.host_only = host_only
 

@@ -34,8 +34,13 @@ def _compile(src, verbose):
 
 
 def build(verbose=False):
-    sys.path.insert(0, os.path.dirname(HERE))
-    from paper_1409_2908_amd.algorithms import gen_tables
+    # load the generator by path: importing the package would load the
+    # (possibly stale) library this build is about to replace
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "fmm_gen_tables", os.path.join(HERE, "algorithms", "gen_tables.py"))
+    gen_tables = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen_tables)
     gen_tables.generate()
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:

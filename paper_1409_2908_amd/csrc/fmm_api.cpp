@@ -195,7 +195,7 @@ hipError_t run_stage(const fmm::Plan& P, int stage, const fmm::Bases& b, hipStre
 }
 
 fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
-                       int dtype, bool device) {
+                       int dtype, int fuse, bool device) {
   if (!out) return fail(FMM_EINVAL, "out is NULL");
   *out = nullptr;
   fmm_status st = check_tables_once();
@@ -205,7 +205,7 @@ fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
   fmm_plan_s* h = new (std::nothrow) fmm_plan_s();
   if (!h) return fail(FMM_ENOMEM, "host allocation failed");
   int code = 0;
-  std::string err = fmm::make_plan(h->P, alg, m, k, n, levels, dtype, &code);
+  std::string err = fmm::make_plan(h->P, alg, m, k, n, levels, dtype, fuse, &code);
   if (!err.empty()) {
     delete h;
     return fail((fmm_status)code, err);
@@ -260,12 +260,19 @@ extern "C" {
 
 fmm_status fmm_plan(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
                     int dtype) {
-  return plan_common(out, alg, m, k, n, levels, dtype, true);
+  return plan_common(out, alg, m, k, n, levels, dtype, 0, true);
 }
 
 fmm_status fmm_plan_host(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, int64_t n,
                          int levels, int dtype) {
-  return plan_common(out, alg, m, k, n, levels, dtype, false);
+  return plan_common(out, alg, m, k, n, levels, dtype, 0, false);
+}
+
+fmm_status fmm_plan_ex(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
+                       int dtype, const fmm_plan_options_t* opts) {
+  const int fuse = opts ? opts->fuse_levels : 0;
+  const bool host_only = opts && opts->host_only;
+  return plan_common(out, alg, m, k, n, levels, dtype, fuse, !host_only);
 }
 
 fmm_status fmm_run_stage(fmm_plan_t p, int stage, const void* A, int64_t lda, const void* B,
@@ -403,6 +410,7 @@ fmm_status fmm_plan_info(fmm_plan_t p, fmm_plan_info_t* info) {
   info->leaf_flops = P.leaf_flops;
   info->classical_flops = 2.0 * (double)P.m * (double)P.k * (double)P.n;
   info->add_bytes = P.add_bytes;
+  info->fuse_levels = P.levels > 0 ? P.fuse : 0;
   info->gemm_min_bytes = P.gemm_min_bytes;
   return FMM_OK;
 }

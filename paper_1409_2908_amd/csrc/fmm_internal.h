@@ -134,6 +134,7 @@ struct Plan {
   int64_t m = 0, k = 0, n = 0;
   int levels = 0;
   int dtype = 0;
+  int fuse = 1;       // recursion levels fused per addition pass
   int elt = ELT_F64;  // element type of A, B, C and the leaf operands
   int64_t m0 = 0, k0 = 0, n0 = 0, ml = 0, kl = 0, nl = 0;
 
@@ -165,7 +166,7 @@ struct Plan {
 // Plans on the host only; fills every field above except the device side.
 // Returns an empty string on success, else the error message (and sets *code).
 std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
-                      int dtype, int* code);
+                      int dtype, int fuse, int* code);
 
 int find_algorithm(const char* name);  // -1 for "classical", -2 unknown
 

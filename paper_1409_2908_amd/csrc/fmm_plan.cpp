@@ -46,11 +46,15 @@ int col_nnz(const signed char* X, int rows, int R, int r, int* where, int* coef)
   return cnt;
 }
 
-// Levels fused per addition pass (1 or 2); FMM_FUSE overrides.
-int fuse_levels() {
+// Levels fused per addition pass (1 or 2).  An explicit request wins, then
+// the FMM_FUSE environment variable; by default two levels are fused only for
+// narrow base cases (R <= 8): fusing wider ones gives each thread hundreds of
+// output streams and measured slower than one level per pass on MI355X.
+int resolve_fuse(int requested, int R) {
+  if (requested == 1 || requested == 2) return requested;
   const char* e = std::getenv("FMM_FUSE");
   if (e && (e[0] == '1' || e[0] == '2') && e[1] == 0) return e[0] - '0';
-  return 1;
+  return R <= 8 ? 2 : 1;
 }
 
 // Splits L levels into passes of at most `fuse` levels.  Operand formation
@@ -90,7 +94,7 @@ std::vector<Ref> plan_side(Plan& P, int side, Arena& ws, std::vector<FormPass>& 
   nodes[0] = Ref{side == 0 ? BUF_A : BUF_B, in_elt, 0, 0, 0, 0, 1.0};
   int depth = 0;
   *materialized = 0;
-  for (int lv : schedule(P.levels, fuse_levels(), true)) {
+  for (int lv : schedule(P.levels, P.fuse, true)) {
     const int d2 = depth + lv;
     const bool final_pass = d2 == P.levels;
     FormPass fp;
@@ -168,11 +172,12 @@ int find_algorithm(const char* name) {
 }
 
 std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
-                      int dtype, int* code) {
+                      int dtype, int fuse, int* code) {
   *code = 1;  // FMM_EINVAL
   if (m < 0 || k < 0 || n < 0) return "sizes must be non-negative";
   if (levels < 0 || levels > 6) return "levels must be in [0, 6]";
   if (dtype < 0 || dtype > 2) return "unknown dtype";
+  if (fuse < 0 || fuse > 2) return "fuse must be 0 (default), 1 or 2";
   const int id = find_algorithm(alg);
   if (id == -2) {
     *code = 5;  // FMM_EALG
@@ -194,6 +199,7 @@ std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n,
     P.K = A.K;
     P.N = A.N;
     P.R = A.R;
+    P.fuse = resolve_fuse(fuse, A.R);
     const int64_t fm = ipow(A.M, P.levels), fk = ipow(A.K, P.levels), fn = ipow(A.N, P.levels);
     P.m0 = m / fm * fm;
     P.k0 = k / fk * fk;
@@ -286,7 +292,7 @@ std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n,
     int64_t node_stride = m_stride, node_ld = m_ld;
     int node_elt = P.elt;
     int depth = L;
-    std::vector<int> sched = schedule(L, fuse_levels(), false);
+    std::vector<int> sched = schedule(L, P.fuse, false);
     for (size_t pi = 0; pi < sched.size(); ++pi) {
       const int lv = sched[pi];
       const int d2 = depth - lv;
