@@ -1,0 +1,223 @@
+// Grouped, persistent leaf GEMM for FP32 operands with BF16x3 products.
+//
+// Each FP32 operand element x is split on its way into LDS into
+//   hi = bf16(x)   and   lo = bf16(x - hi)     (round to nearest even),
+// and every leaf product is accumulated in FP32 by the BF16 matrix cores as
+//   A_hi B_hi + A_hi B_lo + A_lo B_hi
+// (the lo*lo term, below FP32 resolution of the result, is dropped).  The
+// split keeps about 16 significant bits of each operand; the W-combination and
+// the operand sums stay in FP64/FP32 outside this kernel.
+//
+// Work decomposition and scheduling follow the FP64/FP32 kernel: one flat tile
+// space over all problems, ~2 workgroups of 4 wavefronts per CU, 128 x 128
+// tiles, 64 x 64 per wavefront = 4 x 4 blocks of v_mfma_f32_16x16x32_bf16, XCD
+// aware tile order.  K advances 32 per step through double-buffered LDS that
+// holds the hi and lo planes of A (row-major, k contiguous) and of B
+// transposed (n-major, k contiguous), so each lane's MFMA fragment (8
+// consecutive k of one row / column) is one 16-byte LDS read.  Operands are
+// read with raw buffer loads (out-of-range lanes read 0, stores past the
+// edge are dropped).
+#include <hip/hip_runtime.h>
+
+#include "fmm_gemm_common.h"
+#include "fmm_launch.h"
+
+namespace fmm {
+
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
+typedef float f2_t __attribute__((ext_vector_type(2)));
+
+constexpr int XBM = 128, XBN = 128, XBK = 32, XNT = 256;
+constexpr int XKP = XBK + 8;  // LDS row length in bf16 (keeps 16-byte rows, shifts banks)
+
+struct Bf16x3Smem {
+  __bf16 a_hi[2][XBM][XKP];
+  __bf16 a_lo[2][XBM][XKP];
+  __bf16 b_hi[2][XBN][XKP];
+  __bf16 b_lo[2][XBN][XKP];
+};
+
+__device__ __forceinline__ void split(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+__device__ __forceinline__ float load_f32(__amdgpu_buffer_rsrc_t r, int off, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+}
+
+// One 128 x 128 output tile.  PAIR: K is even, so A is read as aligned
+// element pairs (8-byte loads); otherwise element by element.
+template <bool PAIR>
+__device__ __forceinline__ void bf16x3_tile(Bf16x3Smem& sm, const float* A, const float* B, float* C, int lda,
+                                            int ldb, int ldc, int mrem, int nrem, int64_t K, float alpha) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, lg = lane >> 4;
+
+  // A staging: PAIR: 8 pairs per thread (rows ar + 16 j, k = 2 kp, 2 kp + 1);
+  // otherwise 16 singles (rows ar1 + 8 j, k = ak1).
+  const int ar = tid >> 4, kp = tid & 15;
+  const int ar1 = tid >> 5, ak1 = tid & 31;
+  // B staging: column bn, 16 consecutive k from bk0 (two chunks of 8).
+  const int bn = tid & 127, bk0 = (tid >> 7) * 16;
+  const int a_step = uniform_int(PAIR ? 16 * lda * 4 : 8 * lda * 4);
+  const int b_step = uniform_int(ldb * 4);
+  const int a_base = PAIR ? (ar * lda + 2 * kp) * 4 : (ar1 * lda + ak1) * 4;
+  const int a_rows = PAIR ? (mrem - ar + 15) / 16 : (mrem - ar1 + 7) / 8;
+  const int b_base = bn < nrem ? (bk0 * ldb + bn) * 4 : kInvalidOff;
+
+  f4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
+
+  float ra[16], rb[16];
+  auto gload = [&](int64_t k0) {
+    const __amdgpu_buffer_rsrc_t sa = make_rsrc(A + k0);
+    const __amdgpu_buffer_rsrc_t sb = make_rsrc(B + k0 * (int64_t)ldb);
+    const int kr = K - k0 < XBK ? (int)(K - k0) : XBK;
+    if constexpr (PAIR) {
+      const int av = 2 * kp < kr ? a_base : kInvalidOff;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        // the builtin returns a vector_size(8) value: reinterpret its 8 bytes
+        // as two floats (element-wise conversion to another vector kind is
+        // not a reinterpretation)
+        const f2_t v = __builtin_bit_cast(
+            f2_t, __builtin_amdgcn_raw_buffer_load_b64(sa, j < a_rows ? av : kInvalidOff, j * a_step, 0));
+        ra[2 * j] = v.x;
+        ra[2 * j + 1] = v.y;
+      }
+    } else {
+      const int av = ak1 < kr ? a_base : kInvalidOff;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) ra[j] = load_f32(sa, j < a_rows ? av : kInvalidOff, j * a_step);
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) rb[e] = load_f32(sb, bk0 + e < kr ? b_base : kInvalidOff, e * b_step);
+  };
+  auto lstore = [&](int buf) {
+    if constexpr (PAIR) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        __bf16 h0, l0, h1, l1;
+        split(ra[2 * j], h0, l0);
+        split(ra[2 * j + 1], h1, l1);
+        *(bf2_t*)&sm.a_hi[buf][ar + 16 * j][2 * kp] = bf2_t{h0, h1};
+        *(bf2_t*)&sm.a_lo[buf][ar + 16 * j][2 * kp] = bf2_t{l0, l1};
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) split(ra[j], sm.a_hi[buf][ar1 + 8 * j][ak1], sm.a_lo[buf][ar1 + 8 * j][ak1]);
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      bf8_t h, l;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        __bf16 x, y;
+        split(rb[8 * c + e], x, y);
+        h[e] = x;
+        l[e] = y;
+      }
+      *(bf8_t*)&sm.b_hi[buf][bn][bk0 + 8 * c] = h;
+      *(bf8_t*)&sm.b_lo[buf][bn][bk0 + 8 * c] = l;
+    }
+  };
+
+  const int64_t nk = (K + XBK - 1) / XBK;
+  if (nk > 0) {
+    gload(0);
+    lstore(0);
+  }
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nk) gload((kt + 1) * XBK);
+    bf8_t ah[4], al[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ah[i] = *(const bf8_t*)&sm.a_hi[cur][wm * 64 + i * 16 + li][8 * lg];
+      al[i] = *(const bf8_t*)&sm.a_lo[cur][wm * 64 + i * 16 + li][8 * lg];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bf8_t bh = *(const bf8_t*)&sm.b_hi[cur][wn * 64 + j * 16 + li][8 * lg];
+      const bf8_t bl = *(const bf8_t*)&sm.b_lo[cur][wn * 64 + j * 16 + li][8 * lg];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+      }
+    }
+    if (kt + 1 < nk) lstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  const __amdgpu_buffer_rsrc_t sc = make_rsrc(C);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // 16x16 f32 MFMA output: register v of lane l is row 4 (l / 16) + v, column l % 16
+        const int r = wm * 64 + i * 16 + 4 * lg + v;
+        const int c = wn * 64 + j * 16 + li;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, alpha * acc[i][j][v]), sc,
+                                              (r < mrem && c < nrem) ? (r * ldc + c) * 4 : kInvalidOff, 0, 0);
+      }
+}
+
+__global__ void __launch_bounds__(XNT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+gemm_bf16x3_kernel(GemmArgs args) {
+  __shared__ Bf16x3Smem sm;
+  const int64_t G = gridDim.x;
+  const int64_t slot = (int64_t)(blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
+  for (int64_t t = slot; t < args.total_tiles; t += G) {
+    const TileJob job = decode_tile(args, t);
+    const GemmProb pr = args.probs ? args.probs[job.prob] : args.single;
+    int64_t lda, ldb, ldc;
+    const float* A = (const float*)buf_ptr(args.bases, pr.a, &lda) + pr.a.off;
+    const float* B = (const float*)buf_ptr(args.bases, pr.b, &ldb) + pr.b.off;
+    float* C = (float*)buf_ptr(args.bases, pr.c, &ldc) + pr.c.off;
+    A = uniform_ptr(A + (pr.a.row + job.tm * XBM) * lda + pr.a.col);
+    B = uniform_ptr(B + pr.b.row * ldb + pr.b.col + job.tn * XBN);
+    C = uniform_ptr(C + (pr.c.row + job.tm * XBM) * ldc + pr.c.col + job.tn * XBN);
+    const int64_t mr = job.m - job.tm * XBM, nr = job.n - job.tn * XBN;
+    const int mrem = uniform_int(mr < XBM ? (int)mr : XBM);
+    const int nrem = uniform_int(nr < XBN ? (int)nr : XBN);
+    const int ilda = uniform_int((int)lda), ildb = uniform_int((int)ldb), ildc = uniform_int((int)ldc);
+    const float alpha = (float)uniform_double(pr.alpha);
+    // even K and 8-byte aligned rows allow pair loads of A
+    const bool pair = ((job.k | ilda) & 1) == 0 && (((uintptr_t)A) & 7) == 0;
+    if (pair)
+      bf16x3_tile<true>(sm, A, B, C, ilda, ildb, ildc, mrem, nrem, job.k, alpha);
+    else
+      bf16x3_tile<false>(sm, A, B, C, ilda, ildb, ildc, mrem, nrem, job.k, alpha);
+  }
+}
+
+hipError_t launch_gemm_bf16x3(const GemmArgs& a, int num_cus, hipStream_t s) {
+  if (a.total_tiles <= 0) return hipSuccess;
+  static int per_cu = 0;
+  if (!per_cu) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, gemm_bf16x3_kernel, XNT, 0) != hipSuccess || b < 1) b = 1;
+    per_cu = b;
+  }
+  int64_t G = (int64_t)per_cu * num_cus;
+  const int64_t want = (a.total_tiles + 7) / 8 * 8;
+  if (want < G) G = want;
+  if (G < 8) G = 8;
+  G = G / 8 * 8;
+  hipLaunchKernelGGL(gemm_bf16x3_kernel, dim3((unsigned)G), dim3(XNT), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace fmm

@@ -8,12 +8,13 @@
 namespace fmm {
 
 // BF16x3 leaf kernels are compiled in.
-constexpr bool kHaveBf16x3 = false;
+constexpr bool kHaveBf16x3 = true;
 
 hipError_t launch_form(int alg, const FormArgs& a, int side, int lv, int ngroups, hipStream_t s);
 hipError_t launch_combine(int alg, const CombineArgs& a, int lv, int ngroups, hipStream_t s);
 // Grouped GEMM over every problem in `a`; the element type (a.elt) and the
 // dtype (0: FP64 MFMA, 1: FP32 MFMA, 2: BF16x3 MFMA) select the kernel.
 hipError_t launch_gemm(const GemmArgs& a, int dtype, int num_cus, hipStream_t s);
+hipError_t launch_gemm_bf16x3(const GemmArgs& a, int num_cus, hipStream_t s);
 
 }  // namespace fmm

@@ -1,0 +1,104 @@
+"""GPU parity of the FP32 paths: plain FP32 MFMA leaves and BF16x3 leaves.
+
+Tolerances (relative Frobenius error):
+  classical BF16x3 against the binary64 product: 2e-5.  Each operand keeps
+          ~16 significant bits (2^-16 relative split error, the dropped lo*lo
+          term is 2^-16 relative); FP32 accumulation adds ~2^-24 sqrt(k).
+  classical BF16x3 against its emulation (same split, binary64 sums): 5e-6,
+          which a dropped product term (~2^-9) or a truncating split exceeds.
+  fast BF16x3 against the emulated fast algorithm (oracle.bf16x3.fmm: the
+          same static peel, operands rounded once to FP32, emulated BF16x3
+          leaves): 2e-6 * 2^L, the FP32 tolerance.  What remains is FP32
+          rounding of the operand sums and of the accumulation; the split
+          error itself, amplified by the algorithm's coefficients (about
+          1.4e-4 for <4,2,4> at two levels on the row-scaled inputs), is
+          common to both sides and only reported.
+Integer inputs with small magnitude are exact in every path (bf16 holds
+integers up to 256 exactly; FP32 sums stay below 2^24).
+"""
+import numpy as np
+import pytest
+
+import fmm_inputs
+from oracle import bf16x3, classical
+from gpu_util import relf, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1409_2908_amd as lib
+    return lib
+
+
+def _run(F, alg, L, A, B, dtype):
+    m, k = A.shape
+    n = B.shape[1]
+    with F.Plan(alg, m, k, n, L, dtype) as p:
+        return to_host(p.multiply(to_dev(A), to_dev(B)))
+
+
+@pytest.mark.parametrize("shape", [(256, 512, 384), (300, 333, 257), (129, 64, 1000), (1, 7, 5)])
+def test_bf16x3_classical_matches_emulation(F, shape):
+    m, k, n = shape
+    say(f"case bf16x3 gemm {m}x{k}x{n}")
+    A, B = fmm_inputs.operands(11, m, k, n, "uniform", np.float32)
+    C = to_host(F.gemm(to_dev(A), to_dev(B), dtype=F.F32_BF16X3))
+    emu = bf16x3.gemm(A, B)
+    ref = classical.gemm(A, B)
+    e_emu, e_ref = relf(C, emu), relf(C, ref)
+    say(f"  vs emulation {e_emu:.2e}  vs fp64 {e_ref:.2e}")
+    assert e_emu <= 5e-6
+    assert e_ref <= 2e-5
+
+
+@pytest.mark.parametrize("alg,L", [("classical", 0), ("strassen_222_7", 1), ("strassen_222_7", 2),
+                                   ("fmm_424_26", 1), ("fmm_333_23", 1)])
+def test_bf16x3_integer_bit_exact(F, alg, L):
+    if alg == "classical":
+        m, k, n = 200, 301, 150
+    else:
+        from oracle import algorithms
+        a = algorithms.get(alg)
+        m, k, n = a.M ** L * 9 + 1, a.K ** L * 7 + 1, a.N ** L * 8 + 2
+    say(f"case bf16x3 int {alg} L={L} {m}x{k}x{n}")
+    A, B = fmm_inputs.operands(12, m, k, n, "integer", np.float32)
+    C = _run(F, alg, L, A, B, F.F32_BF16X3)
+    assert np.array_equal(C.astype(np.float64), classical.gemm(A, B))
+
+
+@pytest.mark.parametrize("alg,L", [("strassen_222_7", 1), ("strassen_222_7", 2), ("strassen_222_7", 3),
+                                   ("fmm_424_26", 2), ("fmm_323_15", 1), ("fmm_423_20", 1)])
+def test_bf16x3_fast_parity(F, alg, L):
+    from oracle import algorithms
+    a = algorithms.get(alg)
+    m, k, n = a.M ** L * 40 + 3, a.K ** L * 35 + 1, a.N ** L * 30 + 2
+    say(f"case bf16x3 {alg} L={L} {m}x{k}x{n}")
+    A, B = fmm_inputs.operands(13, m, k, n, "normal_rowscaled", np.float32)
+    C = _run(F, alg, L, A, B, F.F32_BF16X3)
+    ref = classical.gemm(A, B)
+    err = relf(C, ref)
+    # per-row view of the dynamic-range stress (reported, loosely bounded)
+    rows_s = fmm_inputs.scaled_rows(13, m, "A")
+    unscaled = np.setdiff1d(np.arange(m), rows_s)
+    row_err = np.linalg.norm(C - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-300)
+    emu = bf16x3.fmm(a, L, A, B)
+    e_emu = relf(C, emu)
+    say(f"  relF={err:.2e} (emulation {relf(emu, ref):.2e}) vs emulation {e_emu:.2e} "
+        f"max row {row_err.max():.2e} unscaled-rows relF={relf(C[unscaled], ref[unscaled]):.2e}")
+    assert e_emu <= 2e-6 * 2 ** L
+    C32 = _run(F, alg, L, A, B, F.F32)
+    err32 = relf(C32, ref)
+    say(f"  plain FP32 relF={err32:.2e}")
+    assert err32 <= 2e-6 * 2 ** L
+
+
+def test_bf16x3_views_and_peels(F):
+    """Odd leaf k (element-wise A loads), single-non-zero views of A, peel strips."""
+    m, k, n = 2 * 151 + 1, 2 * 149 + 1, 2 * 133 + 1
+    A, B = fmm_inputs.operands(14, m, k, n, "uniform", np.float32)
+    C = _run(F, "strassen_222_7", 1, A, B, F.F32_BF16X3)
+    assert relf(C, classical.gemm(A, B)) <= 4e-5

@@ -290,3 +290,69 @@ def test_form_and_combine_reproduce_static_core(name):
     Ms = [classical.gemm(s, t) for s, t in zip(S, T)]
     C = recursive.combine_products(a, L, Ms)
     assert np.array_equal(C, recursive.fmm(a, L, A, B, peel="static"))
+
+
+# --- the BF16x3 emulation ----------------------------------------------------
+
+def test_bf16_round_to_nearest_even():
+    from oracle import bf16x3
+    # 1 + 2^-8 is halfway between bf16 neighbours 1 and 1 + 2^-7: ties to even (1)
+    # 1 + 3*2^-8 is halfway between 1 + 2^-7 and 1 + 2^-6: ties to even (1 + 2^-6)
+    x = np.array([1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -8 + 2 ** -20, -(1 + 2 ** -8), 3.0, 0.0],
+                 dtype=np.float32)
+    want = np.array([1.0, 1 + 2 ** -6, 1 + 2 ** -7, -1.0, 3.0, 0.0], dtype=np.float32)
+    assert np.array_equal(bf16x3.bf16_round(x), want)
+    # brute force over a range: the result is a bf16 value (low 16 bits zero)
+    # and no other bf16 value is strictly closer
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal(2000).astype(np.float32)
+    r = bf16x3.bf16_round(v)
+    assert np.all((r.view(np.uint32) & 0xFFFF) == 0)
+    up = (r.view(np.uint32) + np.uint32(0x10000)).view(np.float32)
+    dn = (r.view(np.uint32) - np.uint32(0x10000)).view(np.float32)
+    err = np.abs(v.astype(np.float64) - r)
+    assert np.all(err <= np.abs(v.astype(np.float64) - up))
+    assert np.all(err <= np.abs(v.astype(np.float64) - dn))
+
+
+def test_bf16x3_split_and_product():
+    from oracle import bf16x3
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(5000).astype(np.float32)
+    hi, lo = bf16x3.split(x)
+    # the pair keeps 16 significant bits: |x - hi - lo| <= 2^-16 |x|
+    rel = np.abs(x.astype(np.float64) - hi - lo) / np.abs(x.astype(np.float64))
+    assert rel.max() <= 2.0 ** -16
+    # values with at most 16 significant bits reconstruct exactly
+    y = (np.round(x.astype(np.float64) * 2 ** 10) / 2 ** 10).astype(np.float32)
+    y = y[np.abs(y) < 32]
+    h2, l2 = bf16x3.split(y)
+    assert np.array_equal(h2.astype(np.float64) + l2, y.astype(np.float64))
+    # integer matrices with entries of at most 8 bits: lo = 0 and the product is exact
+    A = rng.integers(-200, 201, (20, 30)).astype(np.float32)
+    B = rng.integers(-200, 201, (30, 10)).astype(np.float32)
+    assert np.array_equal(bf16x3.gemm(A, B), A.astype(np.float64) @ B.astype(np.float64))
+    # a dropped lo*hi term would be visible at the 2^-8 relative level
+    A = rng.standard_normal((40, 50)).astype(np.float32)
+    B = rng.standard_normal((50, 30)).astype(np.float32)
+    exact = A.astype(np.float64) @ B.astype(np.float64)
+    err = np.linalg.norm(bf16x3.gemm(A, B) - exact) / np.linalg.norm(exact)
+    assert 1e-7 < err < 2e-5
+
+
+@pytest.mark.parametrize("alg,L", [("strassen_222_7", 2), ("fmm_424_26", 1), ("fmm_333_23", 1),
+                                   ("fmm_323_15", 2)])
+def test_bf16x3_fast_emulation_exact_on_small_integers(alg, L):
+    """With small integer entries every operand sum stays an integer below 2^8
+    in magnitude, so the split is exact (lo = 0) and the emulated fast
+    algorithm -- core leaves, peel strips and combination -- must equal the
+    exact product; odd sizes exercise every peel strip."""
+    from oracle import bf16x3
+    a = algorithms.get(alg)
+    m, k, n = a.M ** L * 3 + 1, a.K ** L * 2 + 1, a.N ** L * 3 + 2
+    rng = np.random.default_rng(7)
+    A = rng.integers(-4, 5, (m, k)).astype(np.float32)
+    B = rng.integers(-4, 5, (k, n)).astype(np.float32)
+    assert np.array_equal(bf16x3.fmm(a, L, A, B), A.astype(np.float64) @ B.astype(np.float64))
+    # at zero levels it is the emulated classical product
+    assert np.array_equal(bf16x3.fmm(a, 0, A, B), bf16x3.gemm(A, B))
