@@ -83,6 +83,8 @@ typedef struct {
     double add_bytes;            /* algorithmic bytes moved by the S, T and W stages */
     double gemm_min_bytes;       /* bytes the leaf stage must read and write at least once */
     int fuse_levels;             /* recursion levels formed / combined per addition pass */
+    char alg[32];                /* base case planned ("classical" for a plain GEMM); for
+                                    "auto" the cost model's choice */
 } fmm_plan_info_t;
 
 /* Options of fmm_plan_ex.  Zero-initialise, then set what you need. */
@@ -90,6 +92,12 @@ typedef struct {
     int fuse_levels;   /* 0: library default (2 for base cases with R <= 8, else 1);
                           1 or 2: recursion levels per operand-formation / combination pass */
     int host_only;     /* non-zero: plan on the host only, as fmm_plan_host */
+    int use_graph;     /* non-zero: fmm_multiply records its launches once into a HIP graph
+                          and replays it; a call with other operand pointers or leading
+                          dimensions re-records it (one capture per change).  Ignored while
+                          stage timing is on. */
+    int defer_device_memory; /* non-zero: allocate nothing on the device; the caller binds
+                          fmm_plan_device_bytes(p) bytes with fmm_plan_bind before running */
 } fmm_plan_options_t;
 
 /* Plan C = A*B for an m x k by k x n product with `levels` recursive steps of
@@ -121,12 +129,36 @@ fmm_status fmm_plan_host(fmm_plan_t *out, const char *alg, int64_t m, int64_t k,
 fmm_status fmm_plan_ex(fmm_plan_t *out, const char *alg, int64_t m, int64_t k, int64_t n,
                        int levels, int dtype, const fmm_plan_options_t *opts);
 
+/* Device bytes a plan made with defer_device_memory needs: its workspace
+ * followed (at a 256-byte boundary) by its descriptor tables. */
+size_t fmm_plan_device_bytes(fmm_plan_t p);
+
+/* Gives a defer_device_memory plan the device region mem[0, bytes) (256-byte
+ * aligned, bytes >= fmm_plan_device_bytes(p)) and enqueues the upload of its
+ * descriptor tables on `stream`.  The caller keeps ownership of mem and must
+ * not reuse it while work of the plan is pending; rebinding is allowed between
+ * runs.  FMM_EINVAL for a plan that owns its memory, NULL or misaligned mem,
+ * too few bytes. */
+fmm_status fmm_plan_bind(fmm_plan_t p, void *mem, size_t bytes, void *stream);
+
 /* Enqueue C = A*B on `stream` using plan p.  One multiply may be in flight per
  * plan at a time (the workspace is shared); use one plan per concurrent
  * stream.  Errors: FMM_EINVAL (ld too small, NULL pointer with non-zero size,
  * C overlapping A or B, host-only plan), FMM_EHIP. */
 fmm_status fmm_multiply(fmm_plan_t p, const void *A, int64_t lda, const void *B, int64_t ldb,
                         void *C, int64_t ldc, void *stream);
+
+/* Enqueue count products C[i] = A[i] * B[i], each with its own plan
+ * plans[i] (all on the current device, each plan at most once), as one batch:
+ * the S and T formations of every request, then grouped leaf launches that
+ * hold the leaf products and peel strips of several requests at once (up to
+ * 8 plans per launch, one launch series per dtype; Section 3.1's products are
+ * independent, so any grouping gives the same results bit for bit), then the
+ * combinations.  Per-request arguments and errors as fmm_multiply; on an
+ * argument error nothing is enqueued and the message names the request. */
+fmm_status fmm_multiply_batched(const fmm_plan_t *plans, const void *const *A, const int64_t *lda,
+                                const void *const *B, const int64_t *ldb, void *const *C,
+                                const int64_t *ldc, int count, void *stream);
 
 /* Enqueue only one stage of fmm_multiply (same arguments).  Running the four
  * stages in order is exactly fmm_multiply; a stage reads what the earlier
@@ -181,6 +213,100 @@ fmm_status fmm_algorithm_coeffs(const char *alg, int *M, int *K, int *N, int *R,
 fmm_status fmm_check_algorithms(void);
 
 const char *fmm_last_error(void);
+
+/* ---- Algorithm and depth selection (model) -------------------------------
+ * The paper picks the base case and depth per shape by measurement
+ * (Section 5: the best algorithm depends on the shape, and recursion pays only
+ * while the leaf product stays efficient).  The library's prior is a cost
+ * model, t = leaf_flops / (rate(dtype) * eff(leaf shape)) + add_bytes / BW
+ * + launches * t_launch, where eff counts 128 x 128 tile padding, the last
+ * partial wave of tiles over the compute units and a per-tile fixed cost in
+ * units of K.  fmm_plan with alg "auto" (any base case) or levels -1 (the
+ * given base case) plans the model's best candidate whose workspace fits the
+ * budget (FMM_HBM_BUDGET bytes, env, else 3/4 of the device's free memory, or
+ * of 288 GB on the host).  Measured selection with a cache lives above the
+ * ABI (the Python autotuner times the model's best few). */
+typedef struct {
+    char alg[32];        /* "classical" or a base-case name */
+    int levels;
+    int fuse_levels;
+    double model_ms;     /* predicted time */
+    double leaf_ms, add_ms;
+    size_t workspace_bytes;
+} fmm_candidate_t;
+
+/* Writes up to max candidates for (m, k, n, dtype), best predicted first,
+ * restricted to base case `alg` when it is not NULL and not "auto"; *count
+ * receives the number written.  Candidates whose workspace exceeds
+ * budget_bytes (0 = the default budget above) are left out. */
+fmm_status fmm_rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const char *alg,
+                               size_t budget_bytes, fmm_candidate_t *out, int max, int *count);
+
+/* ---- Serving runtime: continuous batching ---------------------------------
+ * A request queue in front of fmm_multiply_batched.  Requests are admitted in
+ * arrival order while the device arena (workspaces and descriptor tables)
+ * has room and fewer than max_inflight batches are pending; each admitted
+ * batch of up to max_batch requests is enqueued as one fmm_multiply_batched
+ * on the server's stream and followed by one completion event.  Planning of
+ * the next batch on the host overlaps the running batch on the device.  The
+ * caller owns A, B and C of every request and keeps them alive until the
+ * request completes.  Single-threaded: call every fmm_server_* function of
+ * one server from one thread. */
+typedef struct fmm_server_s *fmm_server_t;
+
+typedef struct {
+    size_t arena_bytes;  /* device bytes for workspaces and tables (admission budget) */
+    int max_batch;       /* requests per batch, 1..64 (leaves of up to 8 share a launch) */
+    int max_inflight;    /* batches enqueued and not finished, >= 1 */
+    int fuse_levels;     /* as fmm_plan_options_t */
+} fmm_server_options_t;
+
+typedef struct {
+    int64_t m, k, n;
+    int dtype;
+    const char *alg;     /* NULL or "auto": model choice of base case and depth */
+    int levels;          /* -1: model choice of depth for `alg` */
+    const void *A; int64_t lda;
+    const void *B; int64_t ldb;
+    void *C; int64_t ldc;
+    void *user;          /* returned with the completion */
+} fmm_request_t;
+
+typedef struct {
+    int64_t id;
+    void *user;
+    fmm_status status;   /* FMM_OK, or why the request was not run */
+    double submit_ms;    /* host steady clock, ms since the server was created */
+    double launch_ms;    /* when its batch was enqueued */
+    double done_ms;      /* when its batch's completion event was seen */
+    int batch_size;
+    char alg[32];
+    int levels;
+} fmm_completion_t;
+
+/* Creates a server on the current device; allocates the arena there.  stream
+ * NULL: the server creates its own stream.  FMM_ENOMEM when the arena cannot
+ * be allocated. */
+fmm_status fmm_server_create(fmm_server_t *out, const fmm_server_options_t *opts, void *stream);
+
+/* Queues a request (validated on the host: sizes, dtype, NULL pointers);
+ * *id is its sequence number.  Does not launch anything by itself. */
+fmm_status fmm_server_submit(fmm_server_t s, const fmm_request_t *req, int64_t *id);
+
+/* Makes progress: retires finished batches (frees their arena space) and
+ * admits and launches new batches.  Writes up to max_done completions.  With
+ * wait non-zero it blocks until at least one request completes if any is
+ * pending.  A request that cannot fit the arena even alone, or whose plan
+ * fails, completes with that error status. */
+fmm_status fmm_server_progress(fmm_server_t s, int wait, fmm_completion_t *done, int max_done,
+                               int *num_done);
+
+/* Requests submitted and not yet returned as completions. */
+int64_t fmm_server_pending(fmm_server_t s);
+
+/* Waits for pending batches, then frees everything.  Requests still queued
+ * are dropped.  NULL is accepted. */
+fmm_status fmm_server_destroy(fmm_server_t s);
 
 #ifdef __cplusplus
 }

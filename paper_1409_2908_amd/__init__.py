@@ -12,7 +12,8 @@ import os
 
 import numpy as np
 
-__all__ = ["FmmError", "Plan", "gemm", "algorithm_coeffs", "algorithm_names",
+__all__ = ["FmmError", "Plan", "Server", "gemm", "multiply_batched", "rank_candidates",
+           "algorithm_coeffs", "algorithm_names",
            "check_algorithms", "library_path", "F64", "F32", "F32_BF16X3",
            "STAGE_FORM_S", "STAGE_FORM_T", "STAGE_LEAF", "STAGE_COMBINE", "LOC_A", "LOC_B",
            "LOC_C", "LOC_WORKSPACE"]
@@ -47,11 +48,38 @@ class _Info(ctypes.Structure):
                 ("gemm_tiles", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t),
                 ("leaf_flops", ctypes.c_double), ("classical_flops", ctypes.c_double),
                 ("add_bytes", ctypes.c_double), ("gemm_min_bytes", ctypes.c_double),
-                ("fuse_levels", ctypes.c_int)]
+                ("fuse_levels", ctypes.c_int), ("alg", ctypes.c_char * 32)]
 
 
 class _Options(ctypes.Structure):
-    _fields_ = [("fuse_levels", ctypes.c_int), ("host_only", ctypes.c_int)]
+    _fields_ = [("fuse_levels", ctypes.c_int), ("host_only", ctypes.c_int),
+                ("use_graph", ctypes.c_int), ("defer_device_memory", ctypes.c_int)]
+
+
+class _Candidate(ctypes.Structure):
+    _fields_ = [("alg", ctypes.c_char * 32), ("levels", ctypes.c_int), ("fuse_levels", ctypes.c_int),
+                ("model_ms", ctypes.c_double), ("leaf_ms", ctypes.c_double), ("add_ms", ctypes.c_double),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+class _ServerOptions(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int),
+                ("max_inflight", ctypes.c_int), ("fuse_levels", ctypes.c_int)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("k", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("dtype", ctypes.c_int), ("alg", ctypes.c_char_p), ("levels", ctypes.c_int),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("B", ctypes.c_void_p),
+                ("ldb", ctypes.c_int64), ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64),
+                ("user", ctypes.c_void_p)]
+
+
+class _Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("user", ctypes.c_void_p), ("status", ctypes.c_int),
+                ("submit_ms", ctypes.c_double), ("launch_ms", ctypes.c_double),
+                ("done_ms", ctypes.c_double), ("batch_size", ctypes.c_int),
+                ("alg", ctypes.c_char * 32), ("levels", ctypes.c_int)]
 
 
 def _load():
@@ -59,6 +87,12 @@ def _load():
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run __graft_entry__.build() "
                           "or python paper_1409_2908_amd/build.py")
+    # torch first: its wheel carries its own HIP runtime (soname
+    # libamdhip64.so.7).  Loaded before libfmm.so, that runtime satisfies the
+    # library's dependency, so the process has one HIP runtime; loaded after,
+    # a second runtime would be mapped from the ROCm install and would find
+    # no usable device once torch's runtime holds it.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     i64, i32, vp, dp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_double
     P = ctypes.c_void_p
@@ -68,6 +102,18 @@ def _load():
         "fmm_plan_ex": ([ctypes.POINTER(P), ctypes.c_char_p, i64, i64, i64, i32, i32,
                          ctypes.POINTER(_Options)], i32),
         "fmm_multiply": ([P, vp, i64, vp, i64, vp, i64, vp], i32),
+        "fmm_multiply_batched": ([ctypes.POINTER(P), ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                  ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(vp),
+                                  ctypes.POINTER(i64), i32, vp], i32),
+        "fmm_plan_device_bytes": ([P], ctypes.c_size_t),
+        "fmm_plan_bind": ([P, vp, ctypes.c_size_t, vp], i32),
+        "fmm_rank_candidates": ([i64, i64, i64, i32, ctypes.c_char_p, ctypes.c_size_t,
+                                 ctypes.POINTER(_Candidate), i32, ctypes.POINTER(i32)], i32),
+        "fmm_server_create": ([ctypes.POINTER(P), ctypes.POINTER(_ServerOptions), vp], i32),
+        "fmm_server_submit": ([P, ctypes.POINTER(_Request), ctypes.POINTER(i64)], i32),
+        "fmm_server_progress": ([P, i32, ctypes.POINTER(_Completion), i32, ctypes.POINTER(i32)], i32),
+        "fmm_server_pending": ([P], i64),
+        "fmm_server_destroy": ([P], i32),
         "fmm_run_stage": ([P, i32, vp, i64, vp, i64, vp, i64, vp], i32),
         "fmm_plan_operand": ([P, i32, i64, ctypes.POINTER(i32), ctypes.POINTER(i64),
                               ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
@@ -132,13 +178,18 @@ class Plan:
     """A planned product C = A @ B (``fmm_plan``).  ``host_only`` plans
     (``fmm_plan_host``) can be inspected but not run."""
 
-    def __init__(self, alg, m, k, n, levels, dtype=F64, host_only=False, fuse_levels=0):
+    def __init__(self, alg, m, k, n, levels, dtype=F64, host_only=False, fuse_levels=0,
+                 use_graph=False, defer_device_memory=False):
         self._p = ctypes.c_void_p()
         self.dtype = _dtype_code(dtype)
-        opts = _Options(int(fuse_levels), 1 if host_only else 0)
+        opts = _Options(int(fuse_levels), 1 if host_only else 0, 1 if use_graph else 0,
+                        1 if defer_device_memory else 0)
         _check(_lib.fmm_plan_ex(ctypes.byref(self._p), alg.encode(), m, k, n, levels, self.dtype,
                                 ctypes.byref(opts)))
-        self.alg, self.m, self.k, self.n, self.levels = alg, m, k, n, levels
+        self.m, self.k, self.n = m, k, n
+        inf = self.info
+        # "auto" / levels -1 resolve to the cost model's choice
+        self.alg, self.levels = inf["alg"], inf["levels"]
         self.host_only = host_only
 
     def _elt(self):
@@ -149,7 +200,18 @@ class Plan:
     def info(self):
         inf = _Info()
         _check(_lib.fmm_plan_info(self._p, ctypes.byref(inf)))
-        return {f: getattr(inf, f) for f, _ in _Info._fields_}
+        d = {f: getattr(inf, f) for f, _ in _Info._fields_}
+        d["alg"] = d["alg"].decode()
+        return d
+
+    @property
+    def device_bytes(self):
+        """Bytes fmm_plan_bind needs (workspace + tables) for deferred plans."""
+        return int(_lib.fmm_plan_device_bytes(self._p))
+
+    def bind(self, ptr, nbytes, stream=None):
+        """Bind device memory [ptr, ptr + nbytes) to a defer_device_memory plan."""
+        _check(_lib.fmm_plan_bind(self._p, ctypes.c_void_p(int(ptr)), int(nbytes), _stream_ptr(stream)))
 
     @property
     def workspace_bytes(self):
@@ -238,6 +300,109 @@ def gemm(A, B, C=None, dtype=None, stream=None):
     c, ldc = _mat(C, "C", elt)
     _check(_lib.fmm_gemm(dtype, m, k, n, a, lda, b, ldb, c, ldc, _stream_ptr(stream)))
     return C
+
+
+def multiply_batched(plans, As, Bs, Cs=None, stream=None):
+    """C[i] = A[i] @ B[i] for every i as one batch (fmm_multiply_batched)."""
+    n = len(plans)
+    if Cs is None:
+        Cs = [None] * n
+    if not (len(As) == len(Bs) == len(Cs) == n):
+        raise ValueError("plans, As, Bs and Cs must have the same length")
+    P = (ctypes.c_void_p * n)()
+    pa, pb, pc = (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)()
+    la, lb, lc = (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)()
+    outs = []
+    for i, (p, A, B, C) in enumerate(zip(plans, As, Bs, Cs)):
+        a, lda, b, ldb, c, ldc, C = p._args(A, B, C)
+        P[i] = p._p.value
+        pa[i], pb[i], pc[i] = a.value, b.value, c.value
+        la[i], lb[i], lc[i] = lda, ldb, ldc
+        outs.append(C)
+    _check(_lib.fmm_multiply_batched(P, pa, la, pb, lb, pc, lc, n, _stream_ptr(stream)))
+    return outs
+
+
+def rank_candidates(m, k, n, dtype=F64, alg=None, budget_bytes=0, max_count=64):
+    """The cost model's candidates (fmm_rank_candidates), best predicted first."""
+    out = (_Candidate * max_count)()
+    cnt = ctypes.c_int()
+    _check(_lib.fmm_rank_candidates(m, k, n, _dtype_code(dtype), alg.encode() if alg else None,
+                                    int(budget_bytes), out, max_count, ctypes.byref(cnt)))
+    res = []
+    for c in out[:cnt.value]:
+        d = {f: getattr(c, f) for f, _ in _Candidate._fields_}
+        d["alg"] = d["alg"].decode()
+        res.append(d)
+    return res
+
+
+class Server:
+    """Continuous-batching request server (fmm_server_*).  Keeps the operand
+    tensors of every request alive until its completion has been returned."""
+
+    def __init__(self, arena_bytes, max_batch=8, max_inflight=2, fuse_levels=0, stream=None):
+        self._s = ctypes.c_void_p()
+        opts = _ServerOptions(int(arena_bytes), int(max_batch), int(max_inflight), int(fuse_levels))
+        sp = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        _check(_lib.fmm_server_create(ctypes.byref(self._s), ctypes.byref(opts), sp))
+        self._live = {}
+
+    def submit(self, A, B, C=None, dtype=None, alg=None, levels=-1):
+        """Queue C = A @ B; returns (request id, C)."""
+        import torch
+        if dtype is None:
+            dtype = F64 if A.dtype == torch.float64 else F32
+        dtype = _dtype_code(dtype)
+        elt = torch.float64 if dtype == F64 else torch.float32
+        m, k = A.shape
+        n = B.shape[1]
+        if C is None:
+            C = torch.empty((m, n), dtype=elt, device=A.device)
+        a, lda = _mat(A, "A", elt)
+        b, ldb = _mat(B, "B", elt)
+        c, ldc = _mat(C, "C", elt)
+        algb = alg.encode() if alg else None
+        req = _Request(m, k, n, dtype, algb, int(levels), a, lda, b, ldb, c, ldc, None)
+        rid = ctypes.c_int64()
+        _check(_lib.fmm_server_submit(self._s, ctypes.byref(req), ctypes.byref(rid)))
+        self._live[rid.value] = (A, B, C)
+        return rid.value, C
+
+    def progress(self, wait=False, max_done=1024):
+        """Completions since the last call: dicts with id, status, times (ms)."""
+        out = (_Completion * max_done)()
+        cnt = ctypes.c_int()
+        _check(_lib.fmm_server_progress(self._s, 1 if wait else 0, out, max_done, ctypes.byref(cnt)))
+        res = []
+        for c in out[:cnt.value]:
+            d = {f: getattr(c, f) for f, _ in _Completion._fields_ if f != "user"}
+            d["alg"] = d["alg"].decode()
+            self._live.pop(d["id"], None)
+            res.append(d)
+        return res
+
+    @property
+    def pending(self):
+        return int(_lib.fmm_server_pending(self._s))
+
+    def close(self):
+        if self._s:
+            _check(_lib.fmm_server_destroy(self._s))
+            self._s = ctypes.c_void_p()
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def algorithm_names():

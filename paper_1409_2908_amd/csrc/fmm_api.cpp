@@ -6,9 +6,11 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/fmm.h"
 #include "fmm_internal.h"
@@ -148,16 +150,26 @@ hipError_t run_form(const fmm::Plan& P, const std::vector<fmm::FormPass>& passes
   return hipSuccess;
 }
 
+// Appends plan P's GEMM groups to a (possibly shared) grouped launch, with
+// P's operand bases in slot `slot`.
+void append_leaf(fmm::GemmArgs& a, const fmm::Plan& P, const fmm::Bases& b, int slot) {
+  a.bases[slot] = b;
+  a.elt = P.elt;
+  for (const fmm::GemmGroup& g0 : P.gemm_groups) {
+    fmm::GemmGroup g = g0;
+    g.tile_start += a.total_tiles;
+    g.probs = table_ptr<fmm::GemmProb>(P, P.dev_probs);
+    g.slot = slot;
+    a.groups[a.ngroups++] = g;
+  }
+  a.total_tiles += P.gemm_tiles;
+}
+
 hipError_t run_leaf(const fmm::Plan& P, const fmm::Bases& b, hipStream_t s) {
   if (P.gemm_groups.empty()) return hipSuccess;
   fmm::GemmArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.bases = b;
-  a.probs = table_ptr<fmm::GemmProb>(P, P.dev_probs);
-  a.ngroups = (int)P.gemm_groups.size();
-  a.elt = P.elt;
-  a.total_tiles = P.gemm_tiles;
-  for (size_t i = 0; i < P.gemm_groups.size(); ++i) a.groups[i] = P.gemm_groups[i];
+  append_leaf(a, P, b, 0);
   return fmm::launch_gemm(a, P.dtype, num_cus(P.device), s);
 }
 
@@ -194,14 +206,96 @@ hipError_t run_stage(const fmm::Plan& P, int stage, const fmm::Bases& b, hipStre
   return hipErrorInvalidValue;
 }
 
+constexpr size_t kTableAlign = 256;
+
+size_t table_offset(const fmm::Plan& P) { return (P.ws_bytes + kTableAlign - 1) / kTableAlign * kTableAlign; }
+
+fmm_status check_runnable(const fmm::Plan& P) {
+  if (P.host_only) return fail(FMM_EINVAL, "host-only plan cannot run");
+  if (P.external && !P.dev_table) return fail(FMM_EINVAL, "no device memory bound to the plan (fmm_plan_bind)");
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  if (cur != P.device) return fail(FMM_EINVAL, "plan belongs to another device");
+  return FMM_OK;
+}
+
+void drop_graph(fmm::Plan& P) {
+  if (P.graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)P.graph_exec);
+  P.graph_exec = nullptr;
+  std::memset(&P.graph_key, 0, sizeof(P.graph_key));
+}
+
+// Records the four stages on the plan's private stream into a graph and
+// (re)instantiates the plan's executable graph from it.
+fmm_status capture_graph(fmm::Plan& P, const fmm::Bases& b) {
+  hipError_t e;
+  if (!P.cap_stream) {
+    hipStream_t cs;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+    P.cap_stream = cs;
+  }
+  hipStream_t cs = (hipStream_t)P.cap_stream;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  hipError_t le = hipSuccess;
+  for (int stage = 0; stage < FMM_NUM_STAGES && le == hipSuccess; ++stage) le = run_stage(P, stage, b, cs);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(cs, &g);
+  if (le != hipSuccess || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    drop_graph(P);
+    return hip_fail(le != hipSuccess ? le : e, "graph capture");
+  }
+  if (P.graph_exec) {
+    hipGraphNode_t bad = nullptr;
+    hipGraphExecUpdateResult r;
+    if (hipGraphExecUpdate((hipGraphExec_t)P.graph_exec, g, &bad, &r) != hipSuccess ||
+        r != hipGraphExecUpdateSuccess) {
+      (void)hipGetLastError();
+      drop_graph(P);
+    }
+  }
+  if (!P.graph_exec) {
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    P.graph_exec = ex;
+  }
+  (void)hipGraphDestroy(g);
+  P.graph_key = b;
+  return FMM_OK;
+}
+
 fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
-                       int dtype, int fuse, bool device) {
+                       int dtype, int fuse, bool device, bool defer = false, bool graph = false) {
   if (!out) return fail(FMM_EINVAL, "out is NULL");
   *out = nullptr;
   fmm_status st = check_tables_once();
   if (st != FMM_OK) return st;
   if (dtype == FMM_F32_BF16X3 && !fmm::kHaveBf16x3)
     return fail(FMM_EUNSUPPORTED, "BF16x3 leaves are not available in this build");
+  // "auto" (any base case) or levels -1 (best depth of `alg`): the cost model's choice
+  std::string chosen;
+  if ((alg && !std::strcmp(alg, "auto")) || levels < 0) {
+    if (levels < -1) return fail(FMM_EINVAL, "levels must be >= -1");
+    std::vector<fmm::Candidate> cands;
+    std::string why = fmm::rank_candidates(m, k, n, dtype, alg, 0, fuse, cands);
+    if (!why.empty()) return fail(why.rfind("unknown algorithm", 0) == 0 ? FMM_EALG : FMM_EINVAL, why);
+    const fmm::Candidate* pick = nullptr;
+    for (const fmm::Candidate& c : cands)
+      if (levels < 0 || c.levels == levels) {
+        pick = &c;
+        break;
+      }
+    if (!pick) return fail(FMM_ENOMEM, "no candidate fits the workspace budget");
+    chosen = pick->alg;
+    alg = chosen.c_str();
+    levels = pick->levels;
+  }
   fmm_plan_s* h = new (std::nothrow) fmm_plan_s();
   if (!h) return fail(FMM_ENOMEM, "host allocation failed");
   int code = 0;
@@ -224,6 +318,14 @@ fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
     if (e != hipSuccess) {
       delete h;
       return hip_fail(e, "hipGetDevice");
+    }
+    P.use_graph = graph;
+    if (defer) {
+      // The caller binds device memory (fmm_plan_bind) before the first run.
+      P.external = true;
+      P.host_only = false;
+      *out = h;
+      return FMM_OK;
     }
     if (P.ws_bytes) {
       e = hipMalloc(&P.ws, P.ws_bytes);
@@ -256,6 +358,10 @@ fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
 
 }  // namespace
 
+namespace fmm {
+int set_error(int code, const std::string& msg) { return (int)fail((fmm_status)code, msg); }
+}  // namespace fmm
+
 extern "C" {
 
 fmm_status fmm_plan(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
@@ -272,7 +378,37 @@ fmm_status fmm_plan_ex(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
                        int dtype, const fmm_plan_options_t* opts) {
   const int fuse = opts ? opts->fuse_levels : 0;
   const bool host_only = opts && opts->host_only;
-  return plan_common(out, alg, m, k, n, levels, dtype, fuse, !host_only);
+  const bool defer = opts && opts->defer_device_memory;
+  const bool graph = opts && opts->use_graph;
+  return plan_common(out, alg, m, k, n, levels, dtype, fuse, !host_only, defer, graph);
+}
+
+size_t fmm_plan_device_bytes(fmm_plan_t p) {
+  if (!p) return 0;
+  return table_offset(p->P) + p->P.table_bytes;
+}
+
+fmm_status fmm_plan_bind(fmm_plan_t p, void* mem, size_t bytes, void* stream) {
+  if (!p) return fail(FMM_EINVAL, "plan is NULL");
+  fmm::Plan& P = p->P;
+  if (!P.external) return fail(FMM_EINVAL, "plan owns its device memory (not made with defer_device_memory)");
+  if (!mem) return fail(FMM_EINVAL, "mem is NULL");
+  if ((uintptr_t)mem % kTableAlign) return fail(FMM_EINVAL, "mem must be 256-byte aligned");
+  if (bytes < fmm_plan_device_bytes(p)) return fail(FMM_EINVAL, "bytes < fmm_plan_device_bytes(p)");
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  if (cur != P.device) return fail(FMM_EINVAL, "plan belongs to another device");
+  drop_graph(P);
+  P.ws = P.ws_bytes ? mem : nullptr;
+  P.dev_table = (char*)mem + table_offset(P);
+  hipError_t e = hipMemcpyAsync(P.dev_table, P.table.data(), P.table_bytes, hipMemcpyHostToDevice,
+                                (hipStream_t)stream);
+  if (e != hipSuccess) {
+    P.ws = nullptr;
+    P.dev_table = nullptr;
+    return hip_fail(e, "hipMemcpyAsync of the descriptor table");
+  }
+  return FMM_OK;
 }
 
 fmm_status fmm_run_stage(fmm_plan_t p, int stage, const void* A, int64_t lda, const void* B,
@@ -284,9 +420,8 @@ fmm_status fmm_run_stage(fmm_plan_t p, int stage, const void* A, int64_t lda, co
   fmm_status st = validate(P, A, lda, B, ldb, C, ldc);
   if (st != FMM_OK) return st;
   if (P.m == 0 || P.n == 0) return FMM_OK;
-  int cur = -1;
-  (void)hipGetDevice(&cur);
-  if (cur != P.device) return fail(FMM_EINVAL, "plan belongs to another device");
+  st = check_runnable(P);
+  if (st != FMM_OK) return st;
   const fmm::Bases b = make_bases(P, A, lda, B, ldb, C, ldc);
   hipError_t e = run_stage(P, stage, b, (hipStream_t)stream);
   return e == hipSuccess ? FMM_OK : hip_fail(e, "kernel launch");
@@ -300,11 +435,18 @@ fmm_status fmm_multiply(fmm_plan_t p, const void* A, int64_t lda, const void* B,
   fmm_status st = validate(P, A, lda, B, ldb, C, ldc);
   if (st != FMM_OK) return st;
   if (P.m == 0 || P.n == 0) return FMM_OK;
-  int cur = -1;
-  (void)hipGetDevice(&cur);
-  if (cur != P.device) return fail(FMM_EINVAL, "plan belongs to another device");
+  st = check_runnable(P);
+  if (st != FMM_OK) return st;
   const fmm::Bases b = make_bases(P, A, lda, B, ldb, C, ldc);
   hipStream_t s = (hipStream_t)stream;
+  if (P.use_graph && !P.timing_slots) {
+    if (!P.graph_exec || std::memcmp(&P.graph_key, &b, sizeof(b)) != 0) {
+      st = capture_graph(P, b);
+      if (st != FMM_OK) return st;
+    }
+    hipError_t e = hipGraphLaunch((hipGraphExec_t)P.graph_exec, s);
+    return e == hipSuccess ? FMM_OK : hip_fail(e, "hipGraphLaunch");
+  }
   const size_t slot = P.timing_slots ? (size_t)(P.timed % P.timing_slots) * (FMM_NUM_STAGES + 1) : 0;
   for (int stage = 0; stage < FMM_NUM_STAGES; ++stage) {
     if (P.timing_slots) {
@@ -319,6 +461,60 @@ fmm_status fmm_multiply(fmm_plan_t p, const void* A, int64_t lda, const void* B,
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     ++P.timed;
   }
+  return FMM_OK;
+}
+
+fmm_status fmm_multiply_batched(const fmm_plan_t* plans, const void* const* A, const int64_t* lda,
+                                const void* const* B, const int64_t* ldb, void* const* C,
+                                const int64_t* ldc, int count, void* stream) {
+  if (count < 0) return fail(FMM_EINVAL, "count < 0");
+  if (count == 0) return FMM_OK;
+  if (!plans || !A || !lda || !B || !ldb || !C || !ldc) return fail(FMM_EINVAL, "NULL array");
+  std::vector<int> live;
+  std::vector<fmm::Bases> bases((size_t)count);
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i]) return fail(FMM_EINVAL, "plan " + std::to_string(i) + " is NULL");
+    const fmm::Plan& P = plans[i]->P;
+    fmm_status st = validate(P, A[i], lda[i], B[i], ldb[i], C[i], ldc[i]);
+    if (st != FMM_OK) return fail(st, "request " + std::to_string(i) + ": " + g_err);
+    if (P.m == 0 || P.n == 0) continue;
+    st = check_runnable(P);
+    if (st != FMM_OK) return fail(st, "request " + std::to_string(i) + ": " + g_err);
+    for (int j : live)
+      if (plans[j] == plans[i]) return fail(FMM_EINVAL, "a plan appears twice in one batch (shared workspace)");
+    bases[i] = make_bases(P, A[i], lda[i], B[i], ldb[i], C[i], ldc[i]);
+    live.push_back(i);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  for (int stage : {FMM_STAGE_FORM_S, FMM_STAGE_FORM_T})
+    for (int i : live)
+      if ((e = run_stage(plans[i]->P, stage, bases[i], s)) != hipSuccess) return hip_fail(e, "kernel launch");
+  // Leaves of all requests of one dtype share grouped launches, as many plans
+  // per launch as the argument block holds.
+  for (int dtype = 0; dtype <= 2; ++dtype) {
+    fmm::GemmArgs a;
+    std::memset(&a, 0, sizeof(a));
+    int slots = 0;
+    auto flush = [&]() -> hipError_t {
+      hipError_t fe = hipSuccess;
+      if (slots) fe = fmm::launch_gemm(a, dtype, num_cus(plans[live[0]]->P.device), s);
+      std::memset(&a, 0, sizeof(a));
+      slots = 0;
+      return fe;
+    };
+    for (int i : live) {
+      const fmm::Plan& P = plans[i]->P;
+      if (P.dtype != dtype || P.gemm_groups.empty()) continue;
+      if (slots == fmm::kMaxGemmSlots || a.ngroups + (int)P.gemm_groups.size() > fmm::kMaxGemmGroups)
+        if ((e = flush()) != hipSuccess) return hip_fail(e, "kernel launch");
+      append_leaf(a, P, bases[i], slots++);
+    }
+    if ((e = flush()) != hipSuccess) return hip_fail(e, "kernel launch");
+  }
+  for (int i : live)
+    if ((e = run_stage(plans[i]->P, FMM_STAGE_COMBINE, bases[i], s)) != hipSuccess)
+      return hip_fail(e, "kernel launch");
   return FMM_OK;
 }
 
@@ -412,6 +608,7 @@ fmm_status fmm_plan_info(fmm_plan_t p, fmm_plan_info_t* info) {
   info->add_bytes = P.add_bytes;
   info->fuse_levels = P.levels > 0 ? P.fuse : 0;
   info->gemm_min_bytes = P.gemm_min_bytes;
+  std::snprintf(info->alg, sizeof(info->alg), "%s", P.alg_id < 0 ? "classical" : fmm::alg_info(P.alg_id).name);
   return FMM_OK;
 }
 
@@ -423,8 +620,12 @@ fmm_status fmm_plan_destroy(fmm_plan_t p) {
     int prev = -1;
     (void)hipGetDevice(&prev);
     if (prev != P.device) (void)hipSetDevice(P.device);
-    if (P.ws && hipFree(P.ws) != hipSuccess) st = fail(FMM_EHIP, "hipFree of the workspace failed");
-    if (P.dev_table && hipFree(P.dev_table) != hipSuccess) st = fail(FMM_EHIP, "hipFree of the table failed");
+    drop_graph(P);
+    if (P.cap_stream) (void)hipStreamDestroy((hipStream_t)P.cap_stream);
+    if (!P.external) {
+      if (P.ws && hipFree(P.ws) != hipSuccess) st = fail(FMM_EHIP, "hipFree of the workspace failed");
+      if (P.dev_table && hipFree(P.dev_table) != hipSuccess) st = fail(FMM_EHIP, "hipFree of the table failed");
+    }
     for (void* ev : P.events) (void)hipEventDestroy((hipEvent_t)ev);
     if (prev != P.device && prev >= 0) (void)hipSetDevice(prev);
   }
@@ -451,8 +652,7 @@ fmm_status fmm_gemm(int dtype, int64_t m, int64_t k, int64_t n, const void* A, i
   (void)hipGetDevice(&dev);
   fmm::GemmArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.bases = make_bases(P, A, lda, B, ldb, C, ldc);
-  a.probs = nullptr;
+  a.bases[0] = make_bases(P, A, lda, B, ldb, C, ldc);
   a.single.a = fmm::Ref{fmm::BUF_A, P.elt, 0, 0, 0, 0, 1.0};
   a.single.b = fmm::Ref{fmm::BUF_B, P.elt, 0, 0, 0, 0, 1.0};
   a.single.c = fmm::Ref{fmm::BUF_C, P.elt, 0, 0, 0, 0, 1.0};
@@ -468,6 +668,8 @@ fmm_status fmm_gemm(int dtype, int64_t m, int64_t k, int64_t n, const void* A, i
   g.tiles_n = (n + fmm::kTileN - 1) / fmm::kTileN;
   g.tile_start = 0;
   g.prob_start = 0;
+  g.probs = nullptr;
+  g.slot = 0;
   a.total_tiles = g.tiles_m * g.tiles_n;
   hipError_t e = fmm::launch_gemm(a, dtype, num_cus(dev), (hipStream_t)stream);
   return e == hipSuccess ? FMM_OK : hip_fail(e, "kernel launch");
@@ -499,6 +701,30 @@ fmm_status fmm_check_algorithms(void) {
   std::string why;
   for (int i = 0; i < fmm::kNumAlgorithms; ++i)
     if (!brent_ok(fmm::alg_info(i), &why)) return fail(FMM_EALG, why);
+  return FMM_OK;
+}
+
+fmm_status fmm_rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const char* alg,
+                               size_t budget_bytes, fmm_candidate_t* out, int max, int* count) {
+  if (count) *count = 0;
+  if (max < 0 || (max > 0 && !out)) return fail(FMM_EINVAL, "bad output array");
+  fmm_status st = check_tables_once();
+  if (st != FMM_OK) return st;
+  std::vector<fmm::Candidate> cands;
+  std::string why = fmm::rank_candidates(m, k, n, dtype, alg, budget_bytes, 0, cands);
+  if (!why.empty()) return fail(why.rfind("unknown algorithm", 0) == 0 ? FMM_EALG : FMM_EINVAL, why);
+  const int nout = std::min<int>(max, (int)cands.size());
+  for (int i = 0; i < nout; ++i) {
+    std::memset(&out[i], 0, sizeof(out[i]));
+    std::snprintf(out[i].alg, sizeof(out[i].alg), "%s", cands[i].alg);
+    out[i].levels = cands[i].levels;
+    out[i].fuse_levels = cands[i].fuse;
+    out[i].model_ms = cands[i].model_ms;
+    out[i].leaf_ms = cands[i].leaf_ms;
+    out[i].add_ms = cands[i].add_ms;
+    out[i].workspace_bytes = cands[i].ws_bytes;
+  }
+  if (count) *count = nout;
   return FMM_OK;
 }
 

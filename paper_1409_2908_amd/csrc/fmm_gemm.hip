@@ -78,6 +78,7 @@ struct Mfma<float> {
 template <typename T>
 __global__ void __launch_bounds__(GNT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm_kernel(GemmArgs args) {
+  const GemmArgs* ap = kernarg_args();
   using MF = Mfma<T>;
   using acc_t = typename MF::acc_t;
   constexpr int ES = (int)sizeof(T);
@@ -96,13 +97,13 @@ gemm_kernel(GemmArgs args) {
   const int64_t G = gridDim.x;
   const int64_t slot = (int64_t)(blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
 
-  for (int64_t t = slot; t < args.total_tiles; t += G) {
-    const TileJob job = decode_tile(args, t);
-    const GemmProb pr = args.probs ? args.probs[job.prob] : args.single;
+  for (int64_t t = slot; t < ap->total_tiles; t += G) {
+    const TileJob job = decode_tile(ap, t);
+    const GemmProb pr = job.probs ? job.probs[job.prob] : ap->single;
     int64_t lda, ldb, ldc;
-    const T* A = (const T*)buf_ptr(args.bases, pr.a, &lda) + pr.a.off;
-    const T* B = (const T*)buf_ptr(args.bases, pr.b, &ldb) + pr.b.off;
-    T* C = (T*)buf_ptr(args.bases, pr.c, &ldc) + pr.c.off;
+    const T* A = (const T*)slot_ptr(ap, job.slot, pr.a, &lda) + pr.a.off;
+    const T* B = (const T*)slot_ptr(ap, job.slot, pr.b, &ldb) + pr.b.off;
+    T* C = (T*)slot_ptr(ap, job.slot, pr.c, &ldc) + pr.c.off;
     // Everything below is the same for the whole workgroup; saying so keeps
     // the buffer resources in scalar registers.
     A = uniform_ptr(A + (pr.a.row + job.tm * GBM) * lda + pr.a.col);

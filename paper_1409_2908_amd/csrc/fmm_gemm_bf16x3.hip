@@ -176,16 +176,17 @@ __device__ __forceinline__ void bf16x3_tile(Bf16x3Smem& sm, const float* A, cons
 
 __global__ void __launch_bounds__(XNT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 gemm_bf16x3_kernel(GemmArgs args) {
+  const GemmArgs* ap = kernarg_args();
   __shared__ Bf16x3Smem sm;
   const int64_t G = gridDim.x;
   const int64_t slot = (int64_t)(blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
-  for (int64_t t = slot; t < args.total_tiles; t += G) {
-    const TileJob job = decode_tile(args, t);
-    const GemmProb pr = args.probs ? args.probs[job.prob] : args.single;
+  for (int64_t t = slot; t < ap->total_tiles; t += G) {
+    const TileJob job = decode_tile(ap, t);
+    const GemmProb pr = job.probs ? job.probs[job.prob] : ap->single;
     int64_t lda, ldb, ldc;
-    const float* A = (const float*)buf_ptr(args.bases, pr.a, &lda) + pr.a.off;
-    const float* B = (const float*)buf_ptr(args.bases, pr.b, &ldb) + pr.b.off;
-    float* C = (float*)buf_ptr(args.bases, pr.c, &ldc) + pr.c.off;
+    const float* A = (const float*)slot_ptr(ap, job.slot, pr.a, &lda) + pr.a.off;
+    const float* B = (const float*)slot_ptr(ap, job.slot, pr.b, &ldb) + pr.b.off;
+    float* C = (float*)slot_ptr(ap, job.slot, pr.c, &ldc) + pr.c.off;
     A = uniform_ptr(A + (pr.a.row + job.tm * XBM) * lda + pr.a.col);
     B = uniform_ptr(B + pr.b.row * ldb + pr.b.col + job.tn * XBN);
     C = uniform_ptr(C + (pr.c.row + job.tm * XBM) * ldc + pr.c.col + job.tn * XBN);

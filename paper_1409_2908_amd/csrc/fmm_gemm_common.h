@@ -39,24 +39,37 @@ __device__ __forceinline__ P* uniform_ptr(P* p) {
 }
 
 
+// The launch's argument block, read through the kernel-argument segment
+// pointer (the block is the kernels' only explicit argument, so it starts the
+// segment).  Indexing it at run time then compiles to scalar loads at a
+// computed address; indexing the by-value parameter would copy the whole
+// block to scratch first.
+__device__ __forceinline__ const GemmArgs* kernarg_args() {
+  return (const GemmArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+}
+
+// Base pointer and leading dimension of view r of the plan in `slot`.
+__device__ __forceinline__ char* slot_ptr(const GemmArgs* a, int slot, const Ref& r, int64_t* ld) {
+  const int buf = uniform_int(r.buf);
+  *ld = buf == BUF_WS ? r.ld : a->bases[slot].ld[buf];
+  return (char*)a->bases[slot].ptr[buf];
+}
+
 struct TileJob {
   int64_t m, n, k, tm, tn, prob;
+  const GemmProb* probs;
+  int slot;
 };
 
-__device__ __forceinline__ TileJob decode_tile(const GemmArgs& args, int64_t t) {
-  int64_t gm = 0, gn = 0, gk = 0, tiles_m = 1, tiles_n = 1, tstart = 0, pstart = 0;
-#pragma unroll
-  for (int i = 0; i < kMaxGemmGroups; ++i) {
-    if (i < args.ngroups && t >= args.groups[i].tile_start) {
-      gm = args.groups[i].m;
-      gn = args.groups[i].n;
-      gk = args.groups[i].k;
-      tiles_m = args.groups[i].tiles_m;
-      tiles_n = args.groups[i].tiles_n;
-      tstart = args.groups[i].tile_start;
-      pstart = args.groups[i].prob_start;
-    }
-  }
+__device__ __forceinline__ TileJob decode_tile(const GemmArgs* args, int64_t t) {
+  int gi = 0;
+  for (int i = 1; i < args->ngroups; ++i)
+    if (t >= args->groups[i].tile_start) gi = i;
+  const GemmGroup& g = args->groups[gi];
+  const int64_t gm = g.m, gn = g.n, gk = g.k, tiles_m = g.tiles_m, tiles_n = g.tiles_n;
+  const int64_t tstart = g.tile_start, pstart = g.prob_start;
+  const GemmProb* probs = g.probs;
+  const int slot = g.slot;
   const int64_t lt = t - tstart;
   const int64_t tpp = tiles_m * tiles_n;
   const int64_t pi = lt / tpp;
@@ -73,6 +86,8 @@ __device__ __forceinline__ TileJob decode_tile(const GemmArgs& args, int64_t t) 
   j.tm = first + rin % rows;
   j.tn = rin / rows;
   j.prob = pstart + pi;
+  j.probs = probs;
+  j.slot = slot;
   return j;
 }
 

@@ -80,19 +80,24 @@ struct GemmProb {
 };
 
 // Problems of identical shape; tiles of all groups form one flat index space.
+// A launch may hold the groups of several plans (a batch): each group names
+// its plan's problem array and the slot of that plan's operand bases.
 struct GemmGroup {
   int64_t m, n, k;
   int64_t count;
   int64_t tiles_m, tiles_n;
   int64_t tile_start;  // first flat tile index of this group
-  int64_t prob_start;  // index of the group's first problem in the problem array
+  int64_t prob_start;  // index of the group's first problem in `probs`
+  const GemmProb* probs = nullptr;  // device array; NULL means GemmArgs::single
+  int32_t slot = 0;                 // index into GemmArgs::bases
+  int32_t pad = 0;
 };
 
-constexpr int kMaxGemmGroups = 8;
+constexpr int kMaxGemmGroups = 24;  // groups per launch (a plan has at most 4)
+constexpr int kMaxGemmSlots = 8;    // plans per launch
 
 struct GemmArgs {
-  Bases bases;
-  const GemmProb* probs;  // device array; NULL means the single problem below
+  Bases bases[kMaxGemmSlots];
   GemmProb single;
   int ngroups;
   int elt;
@@ -159,6 +164,11 @@ struct Plan {
   int timing_slots = 0;         // 0: timing off; else ring of this many multiplies
   std::vector<void*> events;    // (stages + 1) HIP events per slot
   int64_t timed = 0;            // timed multiplies since timing was enabled
+  bool external = false;        // device memory bound by the caller (not owned)
+  bool use_graph = false;       // replay the stages as a captured HIP graph
+  void* graph_exec = nullptr;   // hipGraphExec_t of the last capture
+  void* cap_stream = nullptr;   // private stream the capture is recorded on
+  Bases graph_key{};            // operand bases the captured graph was made for
 
   double leaf_flops = 0, add_bytes = 0, gemm_min_bytes = 0;
 };
@@ -169,6 +179,28 @@ std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n,
                       int dtype, int fuse, int* code);
 
 int find_algorithm(const char* name);  // -1 for "classical", -2 unknown
+
+// Sets the calling thread's error message (fmm_last_error); returns code.
+int set_error(int code, const std::string& msg);
+
+// One candidate of the cost model (fmm_tune.cpp).
+struct Candidate {
+  char alg[32];
+  int levels = 0;
+  int fuse = 0;
+  double model_ms = 0, leaf_ms = 0, add_ms = 0;
+  size_t ws_bytes = 0;
+};
+
+// Workspace budget: FMM_HBM_BUDGET (bytes) if set, else 3/4 of the current
+// device's free memory, else 3/4 of 288 GB.
+size_t default_budget();
+
+// Candidates for (m, k, n, dtype), best predicted first; alg NULL or "auto"
+// for every base case, else only that one ("classical" gives the plain GEMM).
+// Returns an error message or "".
+std::string rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const char* alg, size_t budget,
+                            int fuse, std::vector<Candidate>& out);
 
 constexpr int64_t kTileM = 128, kTileN = 128;
 

@@ -1,0 +1,132 @@
+// Cost model for choosing the base case and recursion depth.
+//
+// The paper chooses per shape by measurement and observes that recursion pays
+// only while the leaf multiplication stays on the flat part of its
+// performance curve (Section 5); the model below is the library's prior for
+// that choice.  For each candidate (base case, depth) it builds the host plan
+// and predicts
+//   t = t_leaf + t_add + launches * t_launch
+// where t_leaf walks the grouped launch as the persistent kernel does: every
+// 128 x 128 output tile of a problem with inner dimension k costs (k + kFix)
+// units, the units are spread over `slots` resident workgroups, and the last
+// partial wave costs a whole tile; t_add moves the plan's algorithmic bytes of
+// the formation and combination passes at the measured streaming rate.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+
+namespace {
+
+// Sustained rates of this library's kernels on MI355X at large sizes
+// (classical 16384^3 leaf GEMM; streaming addition kernels).
+constexpr double kRateF64 = 61e12;     // flop/s, FP64 MFMA leaf
+constexpr double kRateF32 = 106e12;    // flop/s, FP32 MFMA leaf
+constexpr double kRateBf16x3 = 242e12; // FP32-equivalent flop/s, BF16x3 leaf
+constexpr double kAddBw = 4.8e12;      // byte/s, formation / combination passes
+constexpr double kLaunch = 6e-6;       // s per kernel launch on a busy stream
+constexpr double kFix = 32;            // per-tile fixed cost, in units of k
+constexpr int kSlots = 512;            // resident leaf workgroups (2 per compute unit)
+constexpr int64_t kMaxLeaves = 60000;  // candidates with more leaves are not planned
+
+double rate(int dtype) { return dtype == 0 ? kRateF64 : dtype == 1 ? kRateF32 : kRateBf16x3; }
+
+void predict(const Plan& P, Candidate& c) {
+  // leaf: tile-work units of every group, quantised to whole waves of the
+  // core group's tile cost
+  double units = 0, wmax = 0, tiles = 0;
+  for (const GemmGroup& g : P.gemm_groups) {
+    const double t = (double)g.tiles_m * g.tiles_n * g.count;
+    const double w = (double)g.k + kFix;
+    units += t * w;
+    tiles += t;
+    wmax = std::max(wmax, w);
+  }
+  double leaf_s = 0;
+  if (tiles > 0) {
+    const double waves = std::ceil(units / (kSlots * wmax));
+    const double per_unit = 2.0 * kTileM * kTileN / (rate(P.dtype) / kSlots);
+    leaf_s = waves * wmax * per_unit;
+  }
+  const double add_s = P.add_bytes / kAddBw;
+  const double launches = 1.0 + P.s_passes.size() + P.t_passes.size() + P.w_passes.size();
+  c.leaf_ms = leaf_s * 1e3;
+  c.add_ms = add_s * 1e3;
+  c.model_ms = (leaf_s + add_s + launches * kLaunch) * 1e3;
+  c.ws_bytes = P.ws_bytes;
+}
+
+}  // namespace
+
+size_t default_budget() {
+  if (const char* b = std::getenv("FMM_HBM_BUDGET")) {
+    const double v = std::atof(b);
+    if (v > 0) return (size_t)v;
+  }
+  size_t free_b = 0, total_b = 0;
+  int n = 0;
+  if (hipGetDeviceCount(&n) == hipSuccess && n > 0 && hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+    return free_b / 4 * 3;
+  (void)hipGetLastError();
+  return (size_t)288e9 / 4 * 3;
+}
+
+std::string rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const char* alg, size_t budget,
+                            int fuse, std::vector<Candidate>& out) {
+  out.clear();
+  if (m < 0 || k < 0 || n < 0) return "sizes must be non-negative";
+  if (dtype < 0 || dtype > 2) return "unknown dtype";
+  if (!budget) budget = default_budget();
+  const bool any = !alg || !std::strcmp(alg, "auto");
+  std::vector<int> ids;
+  if (any) {
+    for (int i = 0; i < kNumAlgorithms; ++i)
+      if (std::strcmp(alg_info(i).name, "classical_222_8")) ids.push_back(i);
+  } else {
+    const int id = find_algorithm(alg);
+    if (id == -2) return std::string("unknown algorithm '") + alg + "'";
+    if (id >= 0) ids.push_back(id);
+  }
+  auto add = [&](const char* name, int levels) {
+    Plan P;
+    int code = 0;
+    if (!make_plan(P, name, m, k, n, levels, dtype, fuse, &code).empty()) return;
+    if (P.ws_bytes > budget) return;
+    Candidate c;
+    std::snprintf(c.alg, sizeof(c.alg), "%s", name);
+    c.levels = levels;
+    c.fuse = P.levels > 0 ? P.fuse : 0;
+    predict(P, c);
+    out.push_back(c);
+  };
+  if (any || find_algorithm(alg) == -1) add("classical", 0);
+  for (int id : ids) {
+    const AlgInfo& a = alg_info(id);
+    if (!any) add(a.name, 0);  // depth 0 of a named base case: the classical product
+    // recurse while every leaf dimension keeps at least 64 rows, columns and
+    // depth (deeper leaves only lose) and the leaf count stays below
+    // kMaxLeaves (planning cost)
+    int64_t fm = 1, fk = 1, fn = 1, leaves = 1;
+    for (int L = 1; L <= 5; ++L) {
+      fm *= a.M;
+      fk *= a.K;
+      fn *= a.N;
+      leaves *= a.R;
+      if (m / fm < 64 || n / fn < 64 || k / fk < 64 || leaves > kMaxLeaves) break;
+      add(a.name, L);
+    }
+  }
+  std::stable_sort(out.begin(), out.end(),
+                   [](const Candidate& x, const Candidate& y) { return x.model_ms < y.model_ms; });
+  return "";
+}
+
+}  // namespace fmm

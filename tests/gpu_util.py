@@ -11,7 +11,8 @@ _hip = None
 def hip():
     global _hip
     if _hip is None:
-        _hip = ctypes.CDLL("libamdhip64.so")
+        import torch  # noqa: F401  (bind to the HIP runtime torch loaded)
+        _hip = ctypes.CDLL("libamdhip64.so.7")
         _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
         _hip.hipMemcpy.restype = ctypes.c_int
         _hip.hipDeviceSynchronize.restype = ctypes.c_int

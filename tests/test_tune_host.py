@@ -1,0 +1,92 @@
+"""Host-side checks of the cost model behind "auto" and levels = -1.
+
+The model is the library's prior for the choice the paper makes by
+measurement (Section 5: the best base case and depth depend on the shape).
+These tests pin what the model must get right by construction: the ordering,
+the classical time at the calibrated rate, budget pruning, the restriction to
+one base case, and that "auto" plans exactly the top candidate.
+"""
+import pytest
+
+import paper_1409_2908_amd as F
+
+
+def test_candidates_sorted_and_cover_the_table():
+    c = F.rank_candidates(16384, 16384, 16384, F.F64)
+    ms = [x["model_ms"] for x in c]
+    assert ms == sorted(ms)
+    have = {(x["alg"], x["levels"]) for x in c}
+    for want in [("classical", 0), ("strassen_222_7", 1), ("strassen_222_7", 3), ("fmm_333_23", 2),
+                 ("fmm_323_15", 2), ("fmm_423_20", 2), ("fmm_424_26", 2)]:
+        assert want in have, want
+    assert ("classical_222_8", 1) not in have  # the rank-8 identity is a test case, not a candidate
+    # classical: 16384 / 128 = 128 x 128 tiles = 32 full waves of 512 workgroups,
+    # each tile (16384 + 32) k-units at the calibrated 61 TF/s
+    cl = next(x for x in c if x["alg"] == "classical")
+    want_ms = 32 * (16384 + 32) * 2 * 128 * 128 / (61e12 / 512) * 1e3
+    assert abs(cl["leaf_ms"] - want_ms) < 1e-6 * want_ms
+    assert cl["add_ms"] == 0 and cl["workspace_bytes"] == 0
+    # fewer leaf flops at the same efficiency: a fast algorithm is predicted faster
+    assert c[0]["alg"] != "classical"
+    for x in c:
+        assert x["model_ms"] >= x["leaf_ms"] + x["add_ms"]
+
+
+def test_budget_prunes_by_workspace():
+    budget = 64 << 20
+    c = F.rank_candidates(4096, 4096, 4096, F.F64, budget_bytes=budget)
+    assert c and all(x["workspace_bytes"] <= budget for x in c)
+    assert ("classical", 0) in {(x["alg"], x["levels"]) for x in c}
+    full = F.rank_candidates(4096, 4096, 4096, F.F64, budget_bytes=1 << 40)
+    assert len(full) > len(c)
+
+
+def test_restricted_to_one_base_case():
+    c = F.rank_candidates(8192, 8192, 8192, F.F32, alg="strassen_222_7")
+    assert {x["alg"] for x in c} == {"strassen_222_7"}
+    assert sorted(x["levels"] for x in c) == [0, 1, 2, 3, 4, 5]
+    # leaf dimensions stay >= 64: 256 / 2^2 = 64, the third level is not offered;
+    # depth 0 (the classical product) is always a candidate
+    c = F.rank_candidates(256, 256, 256, F.F64, alg="strassen_222_7")
+    assert sorted(x["levels"] for x in c) == [0, 1, 2]
+    c = F.rank_candidates(40, 300, 40, F.F64, alg="fmm_424_26")
+    assert [(x["alg"], x["levels"]) for x in c] == [("fmm_424_26", 0)]
+
+
+@pytest.mark.parametrize("shape,dtype", [((9000, 9000, 9000), F.F64), ((16384, 1600, 16384), F.F64),
+                                         ((16384, 16384, 2400), F.F64), ((512, 512, 512), F.F64),
+                                         ((8192, 8192, 8192), F.F32_BF16X3), ((100, 3000, 70), F.F32)])
+def test_auto_plans_the_top_candidate(shape, dtype):
+    top = F.rank_candidates(*shape, dtype)[0]
+    p = F.Plan("auto", *shape, -1, dtype=dtype, host_only=True)
+    assert (p.alg, p.levels) == (top["alg"], top["levels"])
+    assert p.info["alg"] == top["alg"]
+
+
+def test_depth_choice_for_a_given_base_case():
+    best = F.rank_candidates(16384, 16384, 16384, F.F64, alg="fmm_424_26")[0]
+    p = F.Plan("fmm_424_26", 16384, 16384, 16384, -1, host_only=True)
+    assert (p.alg, p.levels) == ("fmm_424_26", best["levels"])
+    # "auto" at a fixed depth picks the best base case of that depth
+    at2 = [x for x in F.rank_candidates(16384, 16384, 16384, F.F64) if x["levels"] == 2][0]
+    p = F.Plan("auto", 16384, 16384, 16384, 2, host_only=True)
+    assert (p.alg, p.levels) == (at2["alg"], 2)
+
+
+def test_model_errors():
+    with pytest.raises(F.FmmError) as e:
+        F.Plan("strassen_222_7", 64, 64, 64, -2, host_only=True)
+    assert e.value.code == 1
+    with pytest.raises(F.FmmError) as e:
+        F.rank_candidates(64, 64, 64, F.F64, alg="no_such_alg")
+    assert e.value.code == 5
+    with pytest.raises(F.FmmError) as e:
+        F.rank_candidates(-1, 64, 64, F.F64)
+    assert e.value.code == 1
+
+
+def test_device_bytes_cover_workspace_and_tables():
+    p = F.Plan("fmm_424_26", 1000, 500, 1000, 2, host_only=True)
+    ws = p.workspace_bytes
+    assert p.device_bytes > (ws + 255) // 256 * 256
+    assert p.device_bytes < ws + 4096 + 256 * p.info["num_gemm_problems"] + 65536
