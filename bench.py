@@ -9,6 +9,9 @@ Prints one JSON line with the effective rate 2mkn/t, the same-GPU classical
 GEMM rate, the leaf GEMM's roofline figures (live HIP events on the launch
 stream), the error on sampled rows against the CPU oracle, and the oracle's
 own rate on those rows as the CPU baseline.
+
+--mode serving replays a Poisson request stream through the serving runtime;
+--mode sweep prints timing tables of the other workloads (one JSON line each).
 """
 import argparse
 import json
@@ -63,6 +66,15 @@ def main():
     ap.add_argument("--dtype", default="f64", choices=["f64"])
     ap.add_argument("--cpu-rows", type=int, default=32, help="rows of the oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="multiply", choices=["multiply", "serving", "sweep"],
+                    help="multiply: the one-line hot-path benchmark (default); serving: the request "
+                         "stream; sweep: timing tables of the square, rectangular and BF16x3 shapes")
+    ap.add_argument("--requests", type=int, default=10000, help="serving: stream length")
+    ap.add_argument("--load", type=float, default=0.8, help="serving: offered load / measured capacity")
+    ap.add_argument("--arena-gb", type=float, default=96.0, help="serving: workspace arena (GB)")
+    ap.add_argument("--max-batch", type=int, default=8)
+    ap.add_argument("--max-inflight", type=int, default=2)
+    ap.add_argument("--sweep", default="square", choices=["square", "rect", "bf16x3"])
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -77,6 +89,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.mode == "serving":
+        return run_serving(args)
+    if args.mode == "sweep":
+        return run_sweep(args)
     n = args.n
     m = k = n
     log(f"[bench] generating {m}x{k} and {k}x{n} FP64 operands")
@@ -184,6 +200,132 @@ def main():
     }
     print(json.dumps(out), flush=True)
     plan.close()
+
+
+def run_serving(args):
+    """Config: a Poisson stream of FP64 / FP32 (BF16x3) requests, each of m, k, n
+    log-uniform on [256, 8192].  Capacity is measured first with every request
+    arriving at once; the stream then arrives at `load` x that capacity.  The
+    same arrivals are served one at a time by the classical GEMM (FIFO, no
+    batching) for comparison.  A seeded subset of the served requests is
+    recomputed alone and must match the result from the mix bit for bit."""
+    import torch
+    from paper_1409_2908_amd import serving
+
+    reqs = serving.make_requests(7, args.requests)
+    log(f"[serving] {len(reqs)} requests; pools on device")
+    pools = serving.Pools(8192 + 4096, seed=3)
+    arena = int(args.arena_gb * 1e9)
+    zeros = np.zeros(len(reqs))
+    common = dict(arena_bytes=arena, max_batch=args.max_batch, max_inflight=args.max_inflight)
+    cap_fast, _ = serving.run_stream(reqs, zeros, pools, **common)
+    log(f"[serving] capacity, fast path: {cap_fast}")
+    cap_cl, _ = serving.run_stream(reqs, zeros, pools, arena_bytes=arena, max_batch=1, max_inflight=1,
+                                   alg="classical", levels=0)
+    log(f"[serving] capacity, one-at-a-time classical: {cap_cl}")
+    rate = args.load * cap_fast["req_per_s"]
+    arr = serving.poisson_arrivals(11, len(reqs), rate)
+    keep = set(int(x) for x in np.random.default_rng(13).choice(len(reqs), min(200, len(reqs)), replace=False))
+    fast, kept = serving.run_stream(reqs, arr, pools, keep=keep, **common)
+    log(f"[serving] Poisson at {rate:.1f} req/s, fast path: {fast}")
+    cl, _ = serving.run_stream(reqs, arr, pools, arena_bytes=arena, max_batch=1, max_inflight=1,
+                               alg="classical", levels=0)
+    log(f"[serving] Poisson at {rate:.1f} req/s, one-at-a-time classical: {cl}")
+    checked = serving.check_alone(kept)
+    log(f"[serving] {checked} requests recomputed alone: bitwise equal")
+    out = {
+        "metric": "serving throughput (requests/s, effective TFLOP/s) and p50/p99 latency",
+        "value": round(fast["req_per_s"], 3), "unit": "requests/s", "n_gpus": 1,
+        "higher_is_better": True, "data": "synthetic", "dtype": "f64+f32(bf16x3)",
+        "config": {"workload": f"{len(reqs)} requests, m,k,n log-uniform [256,8192], FP64/FP32 1:1, "
+                               f"Poisson at {args.load} x capacity", "arena_gb": args.arena_gb,
+                   "max_batch": args.max_batch, "max_inflight": args.max_inflight},
+        "offered_req_per_s": round(rate, 3),
+        "fast": fast, "classical_one_at_a_time": cl,
+        "capacity_fast": cap_fast, "capacity_classical": cap_cl,
+        "alone_vs_mix_checked": checked,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_sweep(args):
+    """Timing tables (one JSON line per shape and candidate): the square FP64
+    shapes with every base case at 1-3 levels, the rectangular FP64 shapes with
+    the autotuner's pick, or FP32 BF16x3 Strassen at 1-3 levels against plain
+    FP32.  Errors per depth come from the GPU tests, which alone use the
+    oracle."""
+    import torch
+    import paper_1409_2908_amd as F
+    from paper_1409_2908_amd import autotune
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def operands(m, k, n, elt):
+        g = torch.Generator(device="cuda").manual_seed(0)
+        A = torch.rand((m, k), dtype=elt, device="cuda", generator=g) * 2 - 1
+        B = torch.rand((k, n), dtype=elt, device="cuda", generator=g) * 2 - 1
+        return A, B, torch.empty((m, n), dtype=elt, device="cuda")
+
+    def emit(rec):
+        print(json.dumps(rec), flush=True)
+
+    if args.sweep == "square":
+        for n in (4096, 8192, 16384):
+            A, B, C = operands(n, n, n, torch.float64)
+            fl = 2.0 * n ** 3
+            cms = timed(lambda: F.gemm(A, B, C))
+            emit({"shape": [n, n, n], "alg": "classical", "levels": 0, "ms": cms, "tflops": fl / cms / 1e9})
+            for alg in ("strassen_222_7", "fmm_333_23", "fmm_323_15", "fmm_424_26"):
+                for L in (1, 2, 3):
+                    try:
+                        p = F.Plan(alg, n, n, n, L, F.F64)
+                    except F.FmmError as e:
+                        emit({"shape": [n, n, n], "alg": alg, "levels": L, "error": str(e)})
+                        continue
+                    ms = timed(lambda: p.multiply(A, B, C))
+                    emit({"shape": [n, n, n], "alg": alg, "levels": L, "ms": ms, "tflops": fl / ms / 1e9,
+                          "speedup": cms / ms, "workspace_gib": p.workspace_bytes / 2 ** 30})
+                    p.close()
+            del A, B, C
+            torch.cuda.empty_cache()
+    elif args.sweep == "rect":
+        for (m, k, n) in ((16384, 1600, 16384), (16384, 16384, 2400), (9000, 9000, 9000)):
+            A, B, C = operands(m, k, n, torch.float64)
+            fl = 2.0 * m * k * n
+            cms = timed(lambda: F.gemm(A, B, C))
+            t = autotune.tune(m, k, n, F.F64, top=6)
+            emit({"shape": [m, k, n], "classical_ms": cms, "classical_tflops": fl / cms / 1e9,
+                  "tuned": {x: t[x] for x in ("alg", "levels", "fuse_levels", "ms", "tflops")},
+                  "speedup": cms / t["ms"], "model_top": F.rank_candidates(m, k, n, F.F64)[0],
+                  "candidates": [{x: c.get(x) for x in ("alg", "levels", "fuse_levels", "model_ms", "ms")}
+                                 for c in t["candidates"]]})
+            del A, B, C
+            torch.cuda.empty_cache()
+    else:
+        for n in (8192, 16384):
+            A, B, C = operands(n, n, n, torch.float32)
+            fl = 2.0 * n ** 3
+            for dt, name in ((F.F32, "fp32"), (F.F32_BF16X3, "bf16x3")):
+                cms = timed(lambda: F.gemm(A, B, C, dtype=dt))
+                emit({"shape": [n, n, n], "path": name, "alg": "classical", "levels": 0, "ms": cms,
+                      "tflops": fl / cms / 1e9})
+                for L in (1, 2, 3):
+                    p = F.Plan("strassen_222_7", n, n, n, L, dt)
+                    ms = timed(lambda: p.multiply(A, B, C))
+                    emit({"shape": [n, n, n], "path": name, "alg": "strassen_222_7", "levels": L, "ms": ms,
+                          "tflops": fl / ms / 1e9, "speedup_vs_same_path_classical": cms / ms})
+                    p.close()
+            del A, B, C
+            torch.cuda.empty_cache()
 
 
 if __name__ == "__main__":

@@ -224,8 +224,9 @@ const char *fmm_last_error(void);
  * units of K.  fmm_plan with alg "auto" (any base case) or levels -1 (the
  * given base case) plans the model's best candidate whose workspace fits the
  * budget (FMM_HBM_BUDGET bytes, env, else 3/4 of the device's free memory, or
- * of 288 GB on the host).  Measured selection with a cache lives above the
- * ABI (the Python autotuner times the model's best few). */
+ * of 288 GB on the host).  A measured choice recorded with fmm_tune_record
+ * for the exact shape takes precedence (the Python autotuner times the
+ * model's best few candidates and records the winner). */
 typedef struct {
     char alg[32];        /* "classical" or a base-case name */
     int levels;
@@ -241,6 +242,16 @@ typedef struct {
  * budget_bytes (0 = the default budget above) are left out. */
 fmm_status fmm_rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const char *alg,
                                size_t budget_bytes, fmm_candidate_t *out, int max, int *count);
+
+/* Records a measured choice for the exact shape (m, k, n, dtype) in a
+ * process-wide table: later fmm_plan calls with alg "auto" and levels -1 for
+ * that shape, and server requests of that shape with alg NULL/"auto" and
+ * levels -1, plan it (when its workspace fits the budget) instead of the
+ * model's pick.  The choice is validated by planning it on the host.
+ * fmm_tune_clear empties the table.  Thread-safe. */
+fmm_status fmm_tune_record(int64_t m, int64_t k, int64_t n, int dtype, const char *alg, int levels,
+                           int fuse_levels);
+fmm_status fmm_tune_clear(void);
 
 /* ---- Serving runtime: continuous batching ---------------------------------
  * A request queue in front of fmm_multiply_batched.  Requests are admitted in

@@ -282,19 +282,17 @@ fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
   std::string chosen;
   if ((alg && !std::strcmp(alg, "auto")) || levels < 0) {
     if (levels < -1) return fail(FMM_EINVAL, "levels must be >= -1");
-    std::vector<fmm::Candidate> cands;
-    std::string why = fmm::rank_candidates(m, k, n, dtype, alg, 0, fuse, cands);
-    if (!why.empty()) return fail(why.rfind("unknown algorithm", 0) == 0 ? FMM_EALG : FMM_EINVAL, why);
-    const fmm::Candidate* pick = nullptr;
-    for (const fmm::Candidate& c : cands)
-      if (levels < 0 || c.levels == levels) {
-        pick = &c;
-        break;
-      }
-    if (!pick) return fail(FMM_ENOMEM, "no candidate fits the workspace budget");
-    chosen = pick->alg;
+    fmm::Candidate pick;
+    std::string why;
+    if (!fmm::choose(m, k, n, dtype, alg, levels, 0, fuse, &pick, &why))
+      return fail(why.rfind("unknown algorithm", 0) == 0 ? FMM_EALG
+                  : why.rfind("no candidate", 0) == 0    ? FMM_ENOMEM
+                                                         : FMM_EINVAL,
+                  why);
+    chosen = pick.alg;
     alg = chosen.c_str();
-    levels = pick->levels;
+    levels = pick.levels;
+    if (!fuse) fuse = pick.fuse;
   }
   fmm_plan_s* h = new (std::nothrow) fmm_plan_s();
   if (!h) return fail(FMM_ENOMEM, "host allocation failed");
@@ -725,6 +723,30 @@ fmm_status fmm_rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const
     out[i].workspace_bytes = cands[i].ws_bytes;
   }
   if (count) *count = nout;
+  return FMM_OK;
+}
+
+fmm_status fmm_tune_record(int64_t m, int64_t k, int64_t n, int dtype, const char* alg, int levels,
+                           int fuse_levels) {
+  if (m < 0 || k < 0 || n < 0) return fail(FMM_EINVAL, "sizes must be non-negative");
+  if (dtype < 0 || dtype > 2) return fail(FMM_EINVAL, "unknown dtype");
+  if (!alg) return fail(FMM_EINVAL, "alg is NULL");
+  if (fmm::find_algorithm(alg) == -2) return fail(FMM_EALG, std::string("unknown algorithm '") + alg + "'");
+  if (levels < 0 || fuse_levels < 0 || fuse_levels > 2) return fail(FMM_EINVAL, "bad levels or fuse_levels");
+  fmm::Plan P;
+  int code = 0;
+  std::string err = fmm::make_plan(P, alg, m, k, n, levels, dtype, fuse_levels, &code);
+  if (!err.empty()) return fail((fmm_status)code, err);
+  fmm::Candidate c;
+  std::snprintf(c.alg, sizeof(c.alg), "%s", alg);
+  c.levels = levels;
+  c.fuse = fuse_levels;
+  fmm::record_tuned(m, k, n, dtype, c);
+  return FMM_OK;
+}
+
+fmm_status fmm_tune_clear(void) {
+  fmm::clear_tuned();
   return FMM_OK;
 }
 

@@ -180,6 +180,20 @@ std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n,
 
 int find_algorithm(const char* name);  // -1 for "classical", -2 unknown
 
+// What make_plan would produce, without its R^L descriptors: the GEMM groups
+// (tiles filled in), the addition bytes, the workspace bytes and the pass
+// counts, computed per pass from view counts in O(levels).  Equal to the
+// corresponding fields of make_plan for every input (a host test checks it).
+struct PlanSummary {
+  int levels = 0, fuse = 0;
+  std::vector<GemmGroup> groups;
+  double add_bytes = 0, leaf_flops = 0;
+  size_t ws_bytes = 0;
+  int form_passes = 0, comb_passes = 0;
+};
+std::string summarize_plan(PlanSummary& S, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
+                           int dtype, int fuse);
+
 // Sets the calling thread's error message (fmm_last_error); returns code.
 int set_error(int code, const std::string& msg);
 
@@ -201,6 +215,19 @@ size_t default_budget();
 // Returns an error message or "".
 std::string rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const char* alg, size_t budget,
                             int fuse, std::vector<Candidate>& out);
+
+// Measured choices recorded by an autotuner (fmm_tune_record), keyed by the
+// exact (m, k, n, dtype).
+void record_tuned(int64_t m, int64_t k, int64_t n, int dtype, const Candidate& c);
+bool lookup_tuned(int64_t m, int64_t k, int64_t n, int dtype, Candidate* c);
+void clear_tuned();
+
+// The plan to make for alg ("auto"/NULL = any base case) at `levels` (-1 =
+// any depth): a recorded measured choice when alg is "auto" and levels -1 and
+// one exists for the shape (and fits the budget), else the model's best.
+// False with *why on failure.
+bool choose(int64_t m, int64_t k, int64_t n, int dtype, const char* alg, int levels, size_t budget, int fuse,
+            Candidate* pick, std::string* why);
 
 constexpr int64_t kTileM = 128, kTileN = 128;
 

@@ -163,6 +163,137 @@ std::vector<Ref> plan_side(Plan& P, int side, Arena& ws, std::vector<FormPass>& 
 
 }  // namespace
 
+// Closed-form mirror of make_plan's accounting (see the header).  Per pass,
+// outputs come in two kinds: those whose digits all name single-non-zero
+// columns stay views of their group (and keep its element type), the rest are
+// written to the workspace.  Counting groups by element type is enough to
+// reproduce every byte and allocation make_plan makes.
+namespace {
+
+struct ArenaSim {
+  size_t used = 0;
+  void alloc_many(int64_t count, size_t bytes) {
+    if (count <= 0) return;
+    const size_t first = (size_t)round_up((int64_t)used, 256);
+    used = first + (size_t)(count - 1) * (size_t)round_up((int64_t)bytes, 256) + bytes;
+  }
+};
+
+int single_columns(const signed char* X, int rows, int R) {
+  int cnt = 0;
+  for (int r = 0; r < R; ++r) {
+    int where = 0, c = 0;
+    if (col_nnz(X, rows, R, r, &where, &c) == 1) ++cnt;
+  }
+  return cnt;
+}
+
+void summarize_side(const AlgInfo& A, int side, int levels, int fuse, int elt, int64_t rows0, int64_t cols0,
+                    ArenaSim& ws, double* bytes, int* passes) {
+  const int BR = side == 0 ? A.M : A.K;
+  const int BC = side == 0 ? A.K : A.N;
+  const int NB = BR * BC;
+  const int64_t ns = single_columns(side == 0 ? A.U : A.V, NB, A.R);
+  // groups whose element type is the path's, and FP64 groups of an FP32 path
+  int64_t g_in = 1, g_f64 = 0;
+  int depth = 0;
+  for (int lv : schedule(levels, fuse, true)) {
+    const int d2 = depth + lv;
+    const bool final_pass = d2 == levels;
+    const int64_t h = rows0 / ipow(BR, d2), w = cols0 / ipow(BC, d2);
+    const int out_elt = final_pass ? elt : ELT_F64;
+    const int64_t nout = ipow(A.R, lv), nv = ipow(ns, lv);
+    // reads: every group reads NB^lv blocks of its element type
+    *bytes += (double)ipow(NB, lv) * h * w * ((double)g_in * elt_size(elt) + (double)g_f64 * 8);
+    // views kept: a group of the path's type keeps nv views; an FP64 group
+    // keeps nv views unless this is the final pass of an FP32 path
+    const bool f64_views = !final_pass || elt == ELT_F64;
+    const int64_t mat = (g_in + g_f64) * (nout - nv) + (f64_views ? 0 : g_f64 * nv);
+    // allocations happen group by group, output by output, all the same size
+    ws.alloc_many(mat, (size_t)h * round_up(w, 16) * elt_size(out_elt));
+    *bytes += (double)mat * h * w * elt_size(out_elt);
+    const int64_t in_views = g_in * nv, f64_kept = f64_views ? g_f64 * nv : 0;
+    if (out_elt == elt) {
+      g_in = in_views + mat + (elt == ELT_F64 ? f64_kept : 0);
+      g_f64 = elt == ELT_F64 ? 0 : f64_kept;
+    } else {  // FP64 outputs on an FP32 path
+      g_in = in_views;
+      g_f64 = f64_kept + mat;
+    }
+    ++*passes;
+    depth = d2;
+  }
+}
+
+}  // namespace
+
+std::string summarize_plan(PlanSummary& S, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
+                           int dtype, int fuse) {
+  S = PlanSummary();
+  if (m < 0 || k < 0 || n < 0) return "sizes must be non-negative";
+  if (levels < 0 || levels > 6) return "levels must be in [0, 6]";
+  if (dtype < 0 || dtype > 2) return "unknown dtype";
+  const int id = find_algorithm(alg);
+  if (id == -2) return std::string("unknown algorithm '") + (alg ? alg : "(null)") + "'";
+  const int elt = dtype == 0 ? ELT_F64 : ELT_F32;
+  const size_t es = elt_size(elt);
+  int L = id < 0 ? 0 : levels;
+  if (m == 0 || n == 0 || k == 0) L = 0;
+  S.levels = L;
+  if (L == 0) {
+    if (m > 0 && n > 0) S.groups.push_back(GemmGroup{m, n, k, 1, 0, 0, 0, 0});
+  } else {
+    const AlgInfo& A = alg_info(id);
+    S.fuse = resolve_fuse(fuse, A.R);
+    const int64_t fm = ipow(A.M, L), fk = ipow(A.K, L), fn = ipow(A.N, L);
+    const int64_t m0 = m / fm * fm, k0 = k / fk * fk, n0 = n / fn * fn;
+    const int64_t ml = m0 / fm, kl = k0 / fk, nl = n0 / fn;
+    if (ml < 1 || kl < 1 || nl < 1) return "recursion depth leaves a leaf dimension < 1";
+    ArenaSim ws;
+    summarize_side(A, 0, L, S.fuse, elt, m0, k0, ws, &S.add_bytes, &S.form_passes);
+    summarize_side(A, 1, L, S.fuse, elt, k0, n0, ws, &S.add_bytes, &S.form_passes);
+    const int64_t nleaves = ipow(A.R, L);
+    const int64_t m_ld = round_up(nl, 16);
+    const int64_t m_stride = round_up(ml * m_ld * (int64_t)es, 256) / (int64_t)es;
+    ws.alloc_many(1, (size_t)m_stride * es * nleaves);
+    S.groups.push_back(GemmGroup{ml, nl, kl, nleaves, 0, 0, 0, 0});
+    const bool has_p = k0 < k;
+    if (has_p) {
+      ws.alloc_many(1, (size_t)m0 * round_up(n0, 16) * es);
+      S.groups.push_back(GemmGroup{m0, n0, k - k0, 1, 0, 0, 0, 0});
+    }
+    if (n0 < n) S.groups.push_back(GemmGroup{m0, n - n0, k, 1, 0, 0, 0, 0});
+    if (m0 < m) S.groups.push_back(GemmGroup{m - m0, n, k, 1, 0, 0, 0, 0});
+    int depth = L;
+    size_t node_es = es;
+    for (int lv : schedule(L, S.fuse, false)) {
+      const int d2 = depth - lv;
+      const int64_t h = m0 / ipow(A.M, depth), w = n0 / ipow(A.N, depth);
+      const int64_t ngroups = ipow(A.R, d2), per = ipow(A.R, lv);
+      S.add_bytes += (double)ngroups * per * h * w * node_es;
+      const int64_t oh = h * ipow(A.M, lv), ow = w * ipow(A.N, lv);
+      if (d2 == 0) {
+        if (has_p) S.add_bytes += (double)m0 * n0 * es;
+        S.add_bytes += (double)m0 * n0 * es;
+      } else {
+        const int64_t o_stride = round_up(oh * round_up(ow, 16) * 8, 256) / 8;
+        ws.alloc_many(1, (size_t)o_stride * 8 * ngroups);
+        S.add_bytes += (double)ngroups * oh * ow * 8;
+        node_es = 8;
+      }
+      ++S.comb_passes;
+      depth = d2;
+    }
+    S.ws_bytes = ws.used;
+  }
+  for (GemmGroup& g : S.groups) {
+    g.tiles_m = (g.m + kTileM - 1) / kTileM;
+    g.tiles_n = (g.n + kTileN - 1) / kTileN;
+    S.leaf_flops += 2.0 * g.m * g.n * g.k * g.count;
+  }
+  return std::string();
+}
+
 int find_algorithm(const char* name) {
   if (!name) return -2;
   if (std::strcmp(name, "classical") == 0) return -1;

@@ -293,19 +293,14 @@ fmm_status fmm_server_submit(fmm_server_t s, const fmm_request_t* req, int64_t* 
   q.submit_ms = s->now_ms();
   const bool auto_alg = !r.alg || !std::strcmp(r.alg, "auto");
   if (auto_alg || r.levels < 0) {
-    std::vector<fmm::Candidate> cands;
-    std::string why = fmm::rank_candidates(r.m, r.k, r.n, r.dtype, auto_alg ? nullptr : r.alg,
-                                           s->opt.arena_bytes, s->opt.fuse_levels, cands);
-    if (!why.empty()) return fail(FMM_EINVAL, why);
-    const fmm::Candidate* pick = nullptr;
-    for (const fmm::Candidate& c : cands)
-      if (r.levels < 0 || c.levels == r.levels) {
-        pick = &c;
-        break;
-      }
-    if (!pick) return fail(FMM_ENOMEM, "no candidate fits the arena");
-    q.alg = pick->alg;
-    q.levels = pick->levels;
+    // a measured choice for the exact shape if one was recorded, else the model
+    fmm::Candidate pick;
+    std::string why;
+    if (!fmm::choose(r.m, r.k, r.n, r.dtype, auto_alg ? nullptr : r.alg, r.levels, s->opt.arena_bytes,
+                     s->opt.fuse_levels, &pick, &why))
+      return fail(why.rfind("no candidate", 0) == 0 ? FMM_ENOMEM : FMM_EINVAL, why);
+    q.alg = pick.alg;
+    q.levels = pick.levels;
   } else {
     q.alg = r.alg;
     q.levels = r.levels;

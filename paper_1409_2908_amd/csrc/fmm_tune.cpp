@@ -3,8 +3,8 @@
 // The paper chooses per shape by measurement and observes that recursion pays
 // only while the leaf multiplication stays on the flat part of its
 // performance curve (Section 5); the model below is the library's prior for
-// that choice.  For each candidate (base case, depth) it builds the host plan
-// and predicts
+// that choice.  For each candidate (base case, depth) it takes the plan's
+// closed-form summary (no descriptors are built) and predicts
 //   t = t_leaf + t_add + launches * t_launch
 // where t_leaf walks the grouped launch as the persistent kernel does: every
 // 128 x 128 output tile of a problem with inner dimension k costs (k + kFix)
@@ -15,6 +15,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -35,15 +38,15 @@ constexpr double kAddBw = 4.8e12;      // byte/s, formation / combination passes
 constexpr double kLaunch = 6e-6;       // s per kernel launch on a busy stream
 constexpr double kFix = 32;            // per-tile fixed cost, in units of k
 constexpr int kSlots = 512;            // resident leaf workgroups (2 per compute unit)
-constexpr int64_t kMaxLeaves = 60000;  // candidates with more leaves are not planned
+constexpr int64_t kMaxLeaves = 60000;  // candidates with more leaves are not offered
 
 double rate(int dtype) { return dtype == 0 ? kRateF64 : dtype == 1 ? kRateF32 : kRateBf16x3; }
 
-void predict(const Plan& P, Candidate& c) {
+void predict(const PlanSummary& P, int dtype, Candidate& c) {
   // leaf: tile-work units of every group, quantised to whole waves of the
-  // core group's tile cost
+  // largest tile cost
   double units = 0, wmax = 0, tiles = 0;
-  for (const GemmGroup& g : P.gemm_groups) {
+  for (const GemmGroup& g : P.groups) {
     const double t = (double)g.tiles_m * g.tiles_n * g.count;
     const double w = (double)g.k + kFix;
     units += t * w;
@@ -53,11 +56,11 @@ void predict(const Plan& P, Candidate& c) {
   double leaf_s = 0;
   if (tiles > 0) {
     const double waves = std::ceil(units / (kSlots * wmax));
-    const double per_unit = 2.0 * kTileM * kTileN / (rate(P.dtype) / kSlots);
+    const double per_unit = 2.0 * kTileM * kTileN / (rate(dtype) / kSlots);
     leaf_s = waves * wmax * per_unit;
   }
   const double add_s = P.add_bytes / kAddBw;
-  const double launches = 1.0 + P.s_passes.size() + P.t_passes.size() + P.w_passes.size();
+  const double launches = 1.0 + P.form_passes + P.comb_passes;
   c.leaf_ms = leaf_s * 1e3;
   c.add_ms = add_s * 1e3;
   c.model_ms = (leaf_s + add_s + launches * kLaunch) * 1e3;
@@ -96,15 +99,14 @@ std::string rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const ch
     if (id >= 0) ids.push_back(id);
   }
   auto add = [&](const char* name, int levels) {
-    Plan P;
-    int code = 0;
-    if (!make_plan(P, name, m, k, n, levels, dtype, fuse, &code).empty()) return;
+    PlanSummary P;
+    if (!summarize_plan(P, name, m, k, n, levels, dtype, fuse).empty()) return;
     if (P.ws_bytes > budget) return;
     Candidate c;
     std::snprintf(c.alg, sizeof(c.alg), "%s", name);
     c.levels = levels;
     c.fuse = P.levels > 0 ? P.fuse : 0;
-    predict(P, c);
+    predict(P, dtype, c);
     out.push_back(c);
   };
   if (any || find_algorithm(alg) == -1) add("classical", 0);
@@ -113,7 +115,7 @@ std::string rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const ch
     if (!any) add(a.name, 0);  // depth 0 of a named base case: the classical product
     // recurse while every leaf dimension keeps at least 64 rows, columns and
     // depth (deeper leaves only lose) and the leaf count stays below
-    // kMaxLeaves (planning cost)
+    // kMaxLeaves (descriptor tables of that size cost planning time)
     int64_t fm = 1, fk = 1, fn = 1, leaves = 1;
     for (int L = 1; L <= 5; ++L) {
       fm *= a.M;
@@ -127,6 +129,59 @@ std::string rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const ch
   std::stable_sort(out.begin(), out.end(),
                    [](const Candidate& x, const Candidate& y) { return x.model_ms < y.model_ms; });
   return "";
+}
+
+namespace {
+using TuneKey = std::tuple<int64_t, int64_t, int64_t, int>;
+std::mutex g_tuned_mu;
+std::map<TuneKey, Candidate>& tuned_table() {
+  static std::map<TuneKey, Candidate> t;
+  return t;
+}
+}  // namespace
+
+void record_tuned(int64_t m, int64_t k, int64_t n, int dtype, const Candidate& c) {
+  std::lock_guard<std::mutex> g(g_tuned_mu);
+  tuned_table()[TuneKey{m, k, n, dtype}] = c;
+}
+
+bool lookup_tuned(int64_t m, int64_t k, int64_t n, int dtype, Candidate* c) {
+  std::lock_guard<std::mutex> g(g_tuned_mu);
+  auto it = tuned_table().find(TuneKey{m, k, n, dtype});
+  if (it == tuned_table().end()) return false;
+  *c = it->second;
+  return true;
+}
+
+void clear_tuned() {
+  std::lock_guard<std::mutex> g(g_tuned_mu);
+  tuned_table().clear();
+}
+
+bool choose(int64_t m, int64_t k, int64_t n, int dtype, const char* alg, int levels, size_t budget, int fuse,
+            Candidate* pick, std::string* why) {
+  const bool any = !alg || !std::strcmp(alg, "auto");
+  if (any && levels < 0) {
+    Candidate c;
+    if (lookup_tuned(m, k, n, dtype, &c)) {
+      PlanSummary P;
+      if (summarize_plan(P, c.alg, m, k, n, c.levels, dtype, c.fuse).empty() &&
+          P.ws_bytes <= (budget ? budget : default_budget())) {
+        *pick = c;
+        return true;
+      }
+    }
+  }
+  std::vector<Candidate> cands;
+  *why = rank_candidates(m, k, n, dtype, alg, budget, fuse, cands);
+  if (!why->empty()) return false;
+  for (const Candidate& c : cands)
+    if (levels < 0 || c.levels == levels) {
+      *pick = c;
+      return true;
+    }
+  *why = "no candidate fits the workspace budget";
+  return false;
 }
 
 }  // namespace fmm

@@ -90,3 +90,62 @@ def test_device_bytes_cover_workspace_and_tables():
     ws = p.workspace_bytes
     assert p.device_bytes > (ws + 255) // 256 * 256
     assert p.device_bytes < ws + 4096 + 256 * p.info["num_gemm_problems"] + 65536
+
+
+def test_recorded_choice_overrides_the_model(tmp_path):
+    from paper_1409_2908_amd import autotune
+    shape = (3000, 2000, 1000)
+    model = F.Plan("auto", *shape, -1, host_only=True)
+    other = ("fmm_423_20", 1) if model.alg != "fmm_423_20" else ("strassen_222_7", 1)
+    try:
+        autotune.record(*shape, F.F64, other[0], other[1], 1)
+        p = F.Plan("auto", *shape, -1, host_only=True)
+        assert (p.alg, p.levels) == other
+        assert p.info["fuse_levels"] == 1
+        # only the exact shape and dtype, and only for "auto" at levels -1
+        top32 = F.rank_candidates(*shape, F.F32)[0]
+        p32 = F.Plan("auto", *shape, -1, dtype=F.F32, host_only=True)
+        assert (p32.alg, p32.levels) == (top32["alg"], top32["levels"])
+        top1 = F.rank_candidates(3001, 2000, 1000, F.F64)[0]
+        p1 = F.Plan("auto", 3001, 2000, 1000, -1, host_only=True)
+        assert (p1.alg, p1.levels) == (top1["alg"], top1["levels"])
+        assert F.Plan("strassen_222_7", *shape, -1, host_only=True).alg == "strassen_222_7"
+        at2 = [c for c in F.rank_candidates(*shape, F.F64) if c["levels"] == 2][0]
+        assert F.Plan("auto", *shape, 2, host_only=True).alg == at2["alg"]
+        autotune.clear()
+        p = F.Plan("auto", *shape, -1, host_only=True)
+        assert (p.alg, p.levels) == (model.alg, model.levels)
+        # a JSON cache replays into the library
+        cache = tmp_path / "tune.json"
+        cache.write_text('{"3000x2000x1000:0": {"alg": "%s", "levels": %d, "fuse_levels": 1, "ms": 1.0}}'
+                         % other)
+        assert autotune.load_cache(str(cache)) == 1
+        assert (F.Plan("auto", *shape, -1, host_only=True).alg) == other[0]
+        with pytest.raises(F.FmmError):
+            autotune.record(*shape, F.F64, "no_such_alg", 1)
+        with pytest.raises(F.FmmError):
+            autotune.record(7, 64, 64, F.F64, "strassen_222_7", 3)  # leaf dimension < 1
+    finally:
+        autotune.clear()
+
+
+@pytest.mark.parametrize("fuse", ["1", "2"])
+@pytest.mark.parametrize("dtype", [F.F64, F.F32])
+def test_model_summary_equals_the_full_plan(fuse, dtype, monkeypatch):
+    """The model prices candidates from a closed-form summary of the plan
+    (no R^L descriptors).  Its workspace and addition bytes must equal what
+    the full planner computes, for every base case, depth, fusion, dtype and
+    peel pattern offered."""
+    monkeypatch.setenv("FMM_FUSE", fuse)
+    shapes = [(16384, 16384, 16384), (9000, 9000, 9000), (16384, 1600, 16384), (16384, 16384, 2400),
+              (1000, 777, 1234), (513, 257, 129), (300, 200, 4000)]
+    checked = 0
+    for shape in shapes:
+        for alg in ["strassen_222_7", "fmm_333_23", "fmm_323_15", "fmm_423_20", "fmm_424_26"]:
+            for c in F.rank_candidates(*shape, dtype, alg=alg, budget_bytes=1 << 50):
+                p = F.Plan(c["alg"], *shape, c["levels"], dtype=dtype, host_only=True)
+                i = p.info
+                assert c["workspace_bytes"] == i["workspace_bytes"], (shape, c)
+                assert abs(c["add_ms"] - i["add_bytes"] / 4.8e12 * 1e3) <= 1e-12 * max(1.0, c["add_ms"])
+                checked += 1
+    assert checked > 60
