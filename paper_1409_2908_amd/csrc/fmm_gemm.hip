@@ -13,8 +13,8 @@
 // unit (so each SIMD runs two wavefronts of different workgroups, whose
 // barriers do not line up and keep the matrix pipe fed).  K advances 16 at a
 // time through a double-buffered LDS stage: global loads for step k+1 are
-// issued before the MFMAs of step k and stored to the other LDS buffer after
-// them, one barrier per step.  Within a K step lane group g of a wavefront
+// issued before the MFMAs of step k and stored to the other LDS buffer before
+// its last quarter of MFMAs, one barrier per step.  Within a K step lane group g of a wavefront
 // supplies k = 4g + kk for MFMA kk (any bijection of k works when A and B use
 // the same one), so each lane reads its A fragment from one LDS row.
 //
@@ -171,8 +171,12 @@ gemm_kernel(GemmArgs args) {
         for (int i = 0; i < TI; ++i)
 #pragma unroll
           for (int j = 0; j < TJ; ++j) acc[i][j] = MF::op(af[i], bf[j], acc[i][j]);
+        // The other buffer's readers all passed the previous barrier, so the
+        // next step's tile can be written now; doing it before the last
+        // sub-step hides the LDS writes behind its MFMAs (the loads issued at
+        // the top of the step have had three sub-steps to land).
+        if (kk == KPL - 2 && kt + 1 < nk) lstore(cur ^ 1);
       }
-      if (kt + 1 < nk) lstore(cur ^ 1);
       __syncthreads();
     }
 
