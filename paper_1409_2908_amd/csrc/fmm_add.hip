@@ -20,18 +20,32 @@ namespace fmm {
 
 constexpr int kAddTX = 64, kAddTY = 4;
 
-__device__ __forceinline__ void store_out(char* ws, int elt, int64_t idx, double v) {
-  if (elt == ELT_F64) ((double*)ws)[idx] = v;
-  else ((float*)ws)[idx] = (float)v;  // one round-to-nearest-even from the FP64 sum
+__device__ __forceinline__ void store_out(char* ws, int elt, int64_t idx, int64_t plane, double v) {
+  if (elt == ELT_F64) {
+    ((double*)ws)[idx] = v;
+  } else if (elt == ELT_F32) {
+    ((float*)ws)[idx] = (float)v;  // one round-to-nearest-even from the FP64 sum
+  } else {
+    // BF16x3 leaf operand: the FP32 value x of the sum, then its split
+    unsigned short hi, lo;
+    split_bits((float)v, &hi, &lo);
+    ((unsigned short*)ws)[idx] = hi;
+    ((unsigned short*)ws)[idx + plane] = lo;
+  }
 }
 
-template <int ID, int SIDE, int LV>
+// OCT: the output is a split T operand stored in k-octets; each wavefront
+// then covers 8 consecutive rows p of 8 consecutive columns q, so every
+// 2-byte store instruction of the wavefront fills 128 contiguous bytes (8
+// whole octets) instead of scattering over 1 KB.
+template <int ID, int SIDE, int LV, bool OCT = false>
 __global__ void __launch_bounds__(kAddTX * kAddTY) form_kernel(FormArgs a) {
   using S = Side<ID, SIDE>;
   constexpr int NB = S::NB, R = S::R, BR = S::BR, BC = S::BC;
   constexpr int NIN = LV == 1 ? NB : NB * NB;
-  const int64_t q = (int64_t)blockIdx.x * kAddTX + threadIdx.x;
-  const int64_t p = (int64_t)blockIdx.y * kAddTY + threadIdx.y;
+  const int t = threadIdx.y * kAddTX + threadIdx.x;
+  const int64_t q = OCT ? (int64_t)blockIdx.x * 32 + (t >> 3) : (int64_t)blockIdx.x * kAddTX + threadIdx.x;
+  const int64_t p = OCT ? (int64_t)blockIdx.y * 8 + (t & 7) : (int64_t)blockIdx.y * kAddTY + threadIdx.y;
   if (q >= a.w || p >= a.h) return;
   const int g = blockIdx.z;
   const Ref src = a.groups[g];
@@ -50,12 +64,14 @@ __global__ void __launch_bounds__(kAddTX * kAddTY) form_kernel(FormArgs a) {
   });
   char* ws = (char*)a.bases.ptr[BUF_WS];
   const int64_t* outs = a.outs + (int64_t)g * a.nout;
-  const int64_t pos = p * a.out_ld + q;
+  // split T operands are stored in k-octets (see Elt): row p, column q
+  const int64_t pos = (SIDE == 1 && a.out_elt == ELT_BF16X2) ? (p >> 3) * a.out_ld + q * 8 + (p & 7)
+                                                            : p * a.out_ld + q;
   if constexpr (LV == 1) {
     static_for<0, R>([&](auto rc) {
       constexpr int r = decltype(rc)::value;
       const int64_t off = outs[r];
-      if (off >= 0) store_out(ws, a.out_elt, off + pos, chain_col<S, r, 1, NB>(x));
+      if (off >= 0) store_out(ws, a.out_elt, off + pos, a.out_plane, chain_col<S, r, 1, NB>(x));
     });
   } else {
     static_for<0, R>([&](auto r1c) {
@@ -69,7 +85,7 @@ __global__ void __launch_bounds__(kAddTX * kAddTY) form_kernel(FormArgs a) {
       static_for<0, R>([&](auto r2c) {
         constexpr int r2 = decltype(r2c)::value;
         const int64_t off = outs[r1 * R + r2];
-        if (off >= 0) store_out(ws, a.out_elt, off + pos, chain_col<S, r2, 1, NB>(y));
+        if (off >= 0) store_out(ws, a.out_elt, off + pos, a.out_plane, chain_col<S, r2, 1, NB>(y));
       });
     });
   }
@@ -186,6 +202,13 @@ __global__ void __launch_bounds__(1024) combine2_kernel(CombineArgs a) {
 template <int ID>
 static hipError_t launch_form_id(const FormArgs& a, int side, int lv, int ngroups, hipStream_t s) {
   dim3 block(kAddTX, kAddTY);
+  if (side == 1 && a.out_elt == ELT_BF16X2) {
+    dim3 grid((unsigned)((a.w + 31) / 32), (unsigned)((a.h + 7) / 8), (unsigned)ngroups);
+    if (lv == 1) hipLaunchKernelGGL((form_kernel<ID, 1, 1, true>), grid, block, 0, s, a);
+    else if (lv == 2) hipLaunchKernelGGL((form_kernel<ID, 1, 2, true>), grid, block, 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((a.w + kAddTX - 1) / kAddTX), (unsigned)((a.h + kAddTY - 1) / kAddTY),
             (unsigned)ngroups);
   if (side == 0 && lv == 1) hipLaunchKernelGGL((form_kernel<ID, 0, 1>), grid, block, 0, s, a);

@@ -142,6 +142,7 @@ hipError_t run_form(const fmm::Plan& P, const std::vector<fmm::FormPass>& passes
     a.h = fp.h;
     a.w = fp.w;
     a.out_ld = fp.out_ld;
+    a.out_plane = fp.out_plane;
     a.out_elt = fp.out_elt;
     a.nout = fp.nout;
     hipError_t e = fmm::launch_form(P.alg_id, a, fp.side, fp.lv, fp.ngroups, s);

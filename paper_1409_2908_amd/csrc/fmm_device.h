@@ -91,6 +91,22 @@ __device__ __forceinline__ double chain_row(const double* mv) {
   return acc;
 }
 
+// bfloat16 bits of a finite FP32 value, rounded to nearest with ties to even
+// on the bit pattern (add 0x7FFF plus the lowest kept bit, drop 16 bits).
+// The hardware conversion does not break ties to even, and the BF16x3 split
+// is defined with round to nearest even.
+__device__ __forceinline__ unsigned short bf16_bits_rne(float x) {
+  const unsigned u = __builtin_bit_cast(unsigned, x);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// The BF16x3 split of x: hi = bf16(x), lo = bf16(x - hi), both to nearest
+// even; x - hi is exact in FP32.
+__device__ __forceinline__ void split_bits(float x, unsigned short* hi, unsigned short* lo) {
+  *hi = bf16_bits_rne(x);
+  *lo = bf16_bits_rne(x - __builtin_bit_cast(float, (unsigned)*hi << 16));
+}
+
 __device__ __forceinline__ char* buf_ptr(const Bases& b, const Ref& r, int64_t* ld) {
   *ld = r.buf == BUF_WS ? r.ld : b.ld[r.buf];
   return (char*)b.ptr[r.buf];

@@ -1,12 +1,16 @@
 // Grouped, persistent leaf GEMM for FP32 operands with BF16x3 products.
 //
-// Each FP32 operand element x is split on its way into LDS into
+// Each FP32 operand element x is carried as
 //   hi = bf16(x)   and   lo = bf16(x - hi)     (round to nearest even),
 // and every leaf product is accumulated in FP32 by the BF16 matrix cores as
 //   A_hi B_hi + A_hi B_lo + A_lo B_hi
 // (the lo*lo term, below FP32 resolution of the result, is dropped).  The
 // split keeps about 16 significant bits of each operand; the W-combination and
-// the operand sums stay in FP64/FP32 outside this kernel.
+// the operand sums stay in FP64/FP32 outside this kernel.  Leaf operands
+// arrive already split (the formation kernels write hi / lo planes), so their
+// tiles go from HBM to LDS as 16-byte groups with no arithmetic; FP32
+// operands (peel strips, the classical product) are split on their way into
+// LDS.
 //
 // Work decomposition and scheduling follow the FP64/FP32 kernel: one flat tile
 // space over all problems, ~2 workgroups of 4 wavefronts per CU, 128 x 128
@@ -39,16 +43,145 @@ struct Bf16x3Smem {
 };
 
 __device__ __forceinline__ void split(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;
-  lo = (__bf16)(x - (float)hi);
+  unsigned short h, l;
+  split_bits(x, &h, &l);
+  hi = __builtin_bit_cast(__bf16, h);
+  lo = __builtin_bit_cast(__bf16, l);
 }
 
 __device__ __forceinline__ float load_f32(__amdgpu_buffer_rsrc_t r, int off, int soff) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
 }
 
-// One 128 x 128 output tile.  PAIR: K is even, so A is read as aligned
-// element pairs (8-byte loads); otherwise element by element.
+typedef unsigned u4_t __attribute__((ext_vector_type(4)));
+
+// Keeps the first `nvalid` (0..8) bf16 elements of an 8-element group held in
+// four dwords (element e in dword e / 2, low half for even e) and zeroes the
+// rest: the part of a 16-byte group past the end of K.
+__device__ __forceinline__ u4_t keep_first(u4_t v, int nvalid) {
+  u4_t r;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const unsigned m = 2 * d + 1 < nvalid ? 0xffffffffu : 2 * d < nvalid ? 0x0000ffffu : 0u;
+    r[d] = v[d] & m;
+  }
+  return r;
+}
+
+// One 128 x 128 output tile of a leaf whose operands were split by the
+// formation kernels: S planes row-major (row stride lda), T planes in
+// k-octets (group stride ldb).  Every 16-byte global load is one MFMA
+// fragment's worth of k and goes to LDS unchanged; no arithmetic precedes the
+// matrix cores except zeroing the part of the last K group past K.
+__device__ __forceinline__ void bf16x3_tile_split(Bf16x3Smem& sm, const __bf16* Ah, const __bf16* Al,
+                                                  const __bf16* Bh, const __bf16* Bl, float* C, int lda,
+                                                  int ldb, int ldc, int mrem, int nrem, int64_t K,
+                                                  float alpha) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, lg = lane >> 4;
+
+  // A: rows ar and ar + 64, k group ak; B: k groups bg and bg + 2, column bn
+  const int ar = tid >> 2, ak = tid & 3;
+  const int bg = tid >> 7, bn = tid & 127;
+  const int a_base = (ar * lda + 8 * ak) * 2;
+  const int a_step = uniform_int(64 * lda * 2);
+  const int b_base = bn < nrem ? (bg * ldb + 8 * bn) * 2 : kInvalidOff;
+  const int b_step = uniform_int(2 * ldb * 2);
+
+  f4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
+
+  u4_t rah[2], ral[2], rbh[2], rbl[2];
+  auto ld16 = [](__amdgpu_buffer_rsrc_t r, int off, int soff) {
+    return __builtin_bit_cast(u4_t, __builtin_amdgcn_raw_buffer_load_b128(r, off, soff, 0));
+  };
+  auto gload = [&](int64_t k0) {
+    const __amdgpu_buffer_rsrc_t sah = make_rsrc(Ah + k0), sal = make_rsrc(Al + k0);
+    const __amdgpu_buffer_rsrc_t sbh = make_rsrc(Bh + (k0 >> 3) * ldb), sbl = make_rsrc(Bl + (k0 >> 3) * ldb);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int ao = (ar + 64 * j < mrem && k0 + 8 * ak < K) ? a_base : kInvalidOff;
+      rah[j] = ld16(sah, ao, j * a_step);
+      ral[j] = ld16(sal, ao, j * a_step);
+      const int bo = k0 + 8 * (bg + 2 * j) < K ? b_base : kInvalidOff;
+      rbh[j] = ld16(sbh, bo, j * b_step);
+      rbl[j] = ld16(sbl, bo, j * b_step);
+    }
+  };
+  auto lstore = [&](int buf, int64_t k0) {
+    if (k0 + XBK > K) {  // last, partial K step (uniform)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int na = (int)(K - k0) - 8 * ak, nb = (int)(K - k0) - 8 * (bg + 2 * j);
+        rah[j] = keep_first(rah[j], na);
+        ral[j] = keep_first(ral[j], na);
+        rbh[j] = keep_first(rbh[j], nb);
+        rbl[j] = keep_first(rbl[j], nb);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      *(u4_t*)&sm.a_hi[buf][ar + 64 * j][8 * ak] = rah[j];
+      *(u4_t*)&sm.a_lo[buf][ar + 64 * j][8 * ak] = ral[j];
+      *(u4_t*)&sm.b_hi[buf][bn][8 * (bg + 2 * j)] = rbh[j];
+      *(u4_t*)&sm.b_lo[buf][bn][8 * (bg + 2 * j)] = rbl[j];
+    }
+  };
+
+  const int64_t nk = (K + XBK - 1) / XBK;
+  if (nk > 0) {
+    gload(0);
+    lstore(0, 0);
+  }
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nk) gload((kt + 1) * XBK);
+    bf8_t ah[4], al[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ah[i] = *(const bf8_t*)&sm.a_hi[cur][wm * 64 + i * 16 + li][8 * lg];
+      al[i] = *(const bf8_t*)&sm.a_lo[cur][wm * 64 + i * 16 + li][8 * lg];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bf8_t bh = *(const bf8_t*)&sm.b_hi[cur][wn * 64 + j * 16 + li][8 * lg];
+      const bf8_t bl = *(const bf8_t*)&sm.b_lo[cur][wn * 64 + j * 16 + li][8 * lg];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+      }
+      // the other buffer is idle (its readers passed the last barrier): write
+      // the next step's tile before the last quarter of the MFMAs
+      if (j == 2 && kt + 1 < nk) lstore(cur ^ 1, (kt + 1) * XBK);
+    }
+    __syncthreads();
+  }
+
+  const __amdgpu_buffer_rsrc_t sc = make_rsrc(C);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wm * 64 + i * 16 + 4 * lg + v;
+        const int c = wn * 64 + j * 16 + li;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, alpha * acc[i][j][v]), sc,
+                                              (r < mrem && c < nrem) ? (r * ldc + c) * 4 : kInvalidOff, 0, 0);
+      }
+}
+
+// One 128 x 128 output tile with FP32 operands (peel strips and the
+// classical product), split on the way into LDS.  PAIR: K is even, so A is
+// read as aligned element pairs (8-byte loads); otherwise element by element.
 template <bool PAIR>
 __device__ __forceinline__ void bf16x3_tile(Bf16x3Smem& sm, const float* A, const float* B, float* C, int lda,
                                             int ldb, int ldc, int mrem, int nrem, int64_t K, float alpha) {
@@ -184,17 +317,26 @@ gemm_bf16x3_kernel(GemmArgs args) {
     const TileJob job = decode_tile(ap, t);
     const GemmProb pr = job.probs ? job.probs[job.prob] : ap->single;
     int64_t lda, ldb, ldc;
-    const float* A = (const float*)slot_ptr(ap, job.slot, pr.a, &lda) + pr.a.off;
-    const float* B = (const float*)slot_ptr(ap, job.slot, pr.b, &ldb) + pr.b.off;
+    const char* abase = slot_ptr(ap, job.slot, pr.a, &lda);
+    const char* bbase = slot_ptr(ap, job.slot, pr.b, &ldb);
     float* C = (float*)slot_ptr(ap, job.slot, pr.c, &ldc) + pr.c.off;
-    A = uniform_ptr(A + (pr.a.row + job.tm * XBM) * lda + pr.a.col);
-    B = uniform_ptr(B + pr.b.row * ldb + pr.b.col + job.tn * XBN);
     C = uniform_ptr(C + (pr.c.row + job.tm * XBM) * ldc + pr.c.col + job.tn * XBN);
     const int64_t mr = job.m - job.tm * XBM, nr = job.n - job.tn * XBN;
     const int mrem = uniform_int(mr < XBM ? (int)mr : XBM);
     const int nrem = uniform_int(nr < XBN ? (int)nr : XBN);
     const int ilda = uniform_int((int)lda), ildb = uniform_int((int)ldb), ildc = uniform_int((int)ldc);
     const float alpha = (float)uniform_double(pr.alpha);
+    if (uniform_int(pr.a.elt) == ELT_BF16X2) {
+      // leaf operands split by the formation kernels (workspace regions, never
+      // views): S rows of lda, T k-octets of ldb; offsets in bf16 elements
+      const __bf16* Ah = uniform_ptr((const __bf16*)abase + pr.a.off + job.tm * XBM * lda);
+      const __bf16* Bh = uniform_ptr((const __bf16*)bbase + pr.b.off + job.tn * XBN * 8);
+      bf16x3_tile_split(sm, Ah, uniform_ptr(Ah + pr.a.plane), Bh, uniform_ptr(Bh + pr.b.plane), C, ilda, ildb,
+                        ildc, mrem, nrem, job.k, alpha);
+      continue;
+    }
+    const float* A = uniform_ptr((const float*)abase + pr.a.off + (pr.a.row + job.tm * XBM) * lda + pr.a.col);
+    const float* B = uniform_ptr((const float*)bbase + pr.b.off + pr.b.row * ldb + pr.b.col + job.tn * XBN);
     // even K and 8-byte aligned rows allow pair loads of A
     const bool pair = ((job.k | ilda) & 1) == 0 && (((uintptr_t)A) & 7) == 0;
     if (pair)

@@ -14,13 +14,20 @@ namespace fmm {
 // (their leading dimensions arrive with each multiply); WS is the workspace.
 enum Buf : int32_t { BUF_A = 0, BUF_B = 1, BUF_C = 2, BUF_WS = 3, BUF_NONE = -1 };
 
-// Element type of a buffer region.
-enum Elt : int32_t { ELT_F64 = 0, ELT_F32 = 1 };
+// Element type of a buffer region.  ELT_BF16X2 is a split FP32 operand of the
+// BF16x3 path: two bfloat16 planes, hi = bf16(x) and lo = bf16(x - hi), the lo
+// plane `plane` elements after the hi plane.  Leaf S operands are split
+// row-major (element (i, j) of a plane at i * ld + j); leaf T operands are
+// split in k-octets (element (k, n) at (k / 8) * ld + n * 8 + k % 8, ld = 8 *
+// columns), so the 8 consecutive k of one column that a matrix-core fragment
+// takes are one 16-byte group in both cases.
+enum Elt : int32_t { ELT_F64 = 0, ELT_F32 = 1, ELT_BF16X2 = 2 };
 
 // A strided matrix view: element (i, j) is at
 //   base[buf] + off + (row + i) * LD + (col + j),  LD = ld[buf] for A/B/C, else ld.
 // alpha scales every element read through the view (single-non-zero columns of
-// U or V become such views instead of copies).
+// U or V become such views instead of copies).  Split regions (ELT_BF16X2)
+// are never views; their addressing is the one described above.
 struct Ref {
   int32_t buf;
   int32_t elt;
@@ -29,6 +36,7 @@ struct Ref {
   int64_t col;
   int64_t ld;
   double alpha;
+  int64_t plane = 0;  // ELT_BF16X2: element offset of the lo plane
 };
 
 struct Bases {
@@ -48,6 +56,7 @@ struct FormPass {
   int64_t h, w;   // output block dims = position grid
   int64_t out_ld;
   int out_elt;
+  int64_t out_plane = 0;  // ELT_BF16X2 outputs: offset of the lo plane
   int ngroups;
   int nout;       // R^lv
   std::vector<Ref> groups;
@@ -112,6 +121,7 @@ struct FormArgs {
   int64_t h, w, out_ld;
   int out_elt;
   int nout;
+  int64_t out_plane;
 };
 
 constexpr int kMaxMN = 16, kMaxR = 32;

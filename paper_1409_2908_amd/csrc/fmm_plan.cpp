@@ -73,6 +73,20 @@ std::vector<int> schedule(int L, int fuse, bool top_down) {
   return s;
 }
 
+// Layout of a split (BF16x3) leaf operand of h x w elements: S (side 0)
+// row-major with rows padded to 8 elements; T (side 1) in k-octets, one group
+// of 8 consecutive rows per `ld` = 8 w elements.  *plane = elements per plane
+// (the lo plane follows the hi plane).
+void split_layout(int side, int64_t h, int64_t w, int64_t* ld, int64_t* plane) {
+  if (side == 0) {
+    *ld = round_up(w, 8);
+    *plane = h * *ld;
+  } else {
+    *ld = 8 * w;
+    *plane = round_up(h, 8) / 8 * *ld;
+  }
+}
+
 struct Node {
   Ref ref;
 };
@@ -97,6 +111,8 @@ std::vector<Ref> plan_side(Plan& P, int side, Arena& ws, std::vector<FormPass>& 
   for (int lv : schedule(P.levels, P.fuse, true)) {
     const int d2 = depth + lv;
     const bool final_pass = d2 == P.levels;
+    // the BF16x3 path writes its leaf operands split (hi / lo planes)
+    const bool split = final_pass && P.dtype == 2;
     FormPass fp;
     fp.side = side;
     fp.lv = lv;
@@ -104,10 +120,14 @@ std::vector<Ref> plan_side(Plan& P, int side, Arena& ws, std::vector<FormPass>& 
     fp.h = rows0 / ipow(BR, d2);
     fp.w = cols0 / ipow(BC, d2);
     fp.out_ld = round_up(fp.w, 16);
-    fp.out_elt = final_pass ? P.elt : ELT_F64;
+    fp.out_elt = split ? ELT_BF16X2 : final_pass ? P.elt : ELT_F64;
     fp.ngroups = (int)nodes.size();
     fp.nout = (int)ipow(R, lv);
-    const size_t region = (size_t)fp.h * fp.out_ld * elt_size(fp.out_elt);
+    size_t region = (size_t)fp.h * fp.out_ld * elt_size(fp.out_elt);
+    if (split) {
+      split_layout(side, fp.h, fp.w, &fp.out_ld, &fp.out_plane);
+      region = (size_t)fp.out_plane * 2 * 2;  // two planes of bf16
+    }
     std::vector<Ref> next;
     next.reserve(nodes.size() * fp.nout);
     for (const Ref& g : nodes) {
@@ -136,7 +156,7 @@ std::vector<Ref> plan_side(Plan& P, int side, Arena& ws, std::vector<FormPass>& 
           row += (int64_t)(where / BC) * bh;
           col += (int64_t)(where % BC) * bw;
         }
-        const bool view_ok = single && (!final_pass || g.elt == P.elt);
+        const bool view_ok = single && !split && (!final_pass || g.elt == P.elt);
         if (view_ok) {
           Ref v = g;
           v.alpha = alpha;
@@ -146,10 +166,12 @@ std::vector<Ref> plan_side(Plan& P, int side, Arena& ws, std::vector<FormPass>& 
           fp.outs.push_back(-1);
         } else {
           const size_t off = ws.alloc(region);
-          Ref v{BUF_WS, fp.out_elt, (int64_t)(off / elt_size(fp.out_elt)), 0, 0, fp.out_ld, 1.0};
+          const size_t es_out = split ? 2 : elt_size(fp.out_elt);
+          Ref v{BUF_WS, fp.out_elt, (int64_t)(off / es_out), 0, 0, fp.out_ld, 1.0};
+          v.plane = fp.out_plane;
           next.push_back(v);
           fp.outs.push_back(v.off);
-          *bytes += (double)fp.h * fp.w * elt_size(fp.out_elt);
+          *bytes += (double)fp.h * fp.w * (split ? 4 : elt_size(fp.out_elt));
           if (final_pass) ++*materialized;
         }
       }
@@ -188,8 +210,8 @@ int single_columns(const signed char* X, int rows, int R) {
   return cnt;
 }
 
-void summarize_side(const AlgInfo& A, int side, int levels, int fuse, int elt, int64_t rows0, int64_t cols0,
-                    ArenaSim& ws, double* bytes, int* passes) {
+void summarize_side(const AlgInfo& A, int side, int levels, int fuse, int dtype, int elt, int64_t rows0,
+                    int64_t cols0, ArenaSim& ws, double* bytes, int* passes) {
   const int BR = side == 0 ? A.M : A.K;
   const int BC = side == 0 ? A.K : A.N;
   const int NB = BR * BC;
@@ -200,18 +222,27 @@ void summarize_side(const AlgInfo& A, int side, int levels, int fuse, int elt, i
   for (int lv : schedule(levels, fuse, true)) {
     const int d2 = depth + lv;
     const bool final_pass = d2 == levels;
+    const bool split = final_pass && dtype == 2;
     const int64_t h = rows0 / ipow(BR, d2), w = cols0 / ipow(BC, d2);
     const int out_elt = final_pass ? elt : ELT_F64;
-    const int64_t nout = ipow(A.R, lv), nv = ipow(ns, lv);
+    const int64_t nout = ipow(A.R, lv), nv = split ? 0 : ipow(ns, lv);
     // reads: every group reads NB^lv blocks of its element type
     *bytes += (double)ipow(NB, lv) * h * w * ((double)g_in * elt_size(elt) + (double)g_f64 * 8);
     // views kept: a group of the path's type keeps nv views; an FP64 group
-    // keeps nv views unless this is the final pass of an FP32 path
+    // keeps nv views unless this is the final pass of an FP32 path; split
+    // outputs are never views
     const bool f64_views = !final_pass || elt == ELT_F64;
     const int64_t mat = (g_in + g_f64) * (nout - nv) + (f64_views ? 0 : g_f64 * nv);
     // allocations happen group by group, output by output, all the same size
-    ws.alloc_many(mat, (size_t)h * round_up(w, 16) * elt_size(out_elt));
-    *bytes += (double)mat * h * w * elt_size(out_elt);
+    if (split) {
+      int64_t sld = 0, plane = 0;
+      split_layout(side, h, w, &sld, &plane);
+      ws.alloc_many(mat, (size_t)plane * 4);
+      *bytes += (double)mat * h * w * 4;
+    } else {
+      ws.alloc_many(mat, (size_t)h * round_up(w, 16) * elt_size(out_elt));
+      *bytes += (double)mat * h * w * elt_size(out_elt);
+    }
     const int64_t in_views = g_in * nv, f64_kept = f64_views ? g_f64 * nv : 0;
     if (out_elt == elt) {
       g_in = in_views + mat + (elt == ELT_F64 ? f64_kept : 0);
@@ -250,8 +281,8 @@ std::string summarize_plan(PlanSummary& S, const char* alg, int64_t m, int64_t k
     const int64_t ml = m0 / fm, kl = k0 / fk, nl = n0 / fn;
     if (ml < 1 || kl < 1 || nl < 1) return "recursion depth leaves a leaf dimension < 1";
     ArenaSim ws;
-    summarize_side(A, 0, L, S.fuse, elt, m0, k0, ws, &S.add_bytes, &S.form_passes);
-    summarize_side(A, 1, L, S.fuse, elt, k0, n0, ws, &S.add_bytes, &S.form_passes);
+    summarize_side(A, 0, L, S.fuse, dtype, elt, m0, k0, ws, &S.add_bytes, &S.form_passes);
+    summarize_side(A, 1, L, S.fuse, dtype, elt, k0, n0, ws, &S.add_bytes, &S.form_passes);
     const int64_t nleaves = ipow(A.R, L);
     const int64_t m_ld = round_up(nl, 16);
     const int64_t m_stride = round_up(ml * m_ld * (int64_t)es, 256) / (int64_t)es;

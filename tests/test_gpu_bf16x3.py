@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 import fmm_inputs
-from oracle import bf16x3, classical
+from oracle import algorithms, bf16x3, classical
 from gpu_util import relf, say, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
@@ -102,3 +102,53 @@ def test_bf16x3_views_and_peels(F):
     A, B = fmm_inputs.operands(14, m, k, n, "uniform", np.float32)
     C = _run(F, "strassen_222_7", 1, A, B, F.F32_BF16X3)
     assert relf(C, classical.gemm(A, B)) <= 4e-5
+
+
+def _bf16_bits(x32):
+    return (np.ascontiguousarray(x32, dtype=np.float32).view(np.uint32) >> 16).astype(np.uint16)
+
+
+@pytest.mark.parametrize("alg,L", [("strassen_222_7", 1), ("strassen_222_7", 2), ("fmm_424_26", 1),
+                                   ("fmm_333_23", 1), ("fmm_423_20", 2)])
+def test_split_leaf_operands_bit_exact(F, alg, L):
+    """On the BF16x3 path the formation kernels write every leaf operand as
+    hi / lo bfloat16 planes: S row-major, T in k-octets (8 consecutive k of a
+    column together).  Both planes must equal the split of the oracle's chain
+    (binary64, ascending index, level by level) rounded once to FP32, bit for
+    bit; leaf k = 9 exercises a partial octet."""
+    from oracle import recursive
+    from gpu_util import ws_read
+    a = algorithms.get(alg)
+    m, k, n = a.M ** L * 5, a.K ** L * 9, a.N ** L * 6
+    say(f"case split operands {alg} L={L} {m}x{k}x{n}")
+    A, B = fmm_inputs.operands(15, m, k, n, "normal_rowscaled", np.float32)
+    S = recursive.form_operands(a, L, A.astype(np.float64), "A")
+    T = recursive.form_operands(a, L, B.astype(np.float64), "B")
+    with F.Plan(alg, m, k, n, L, F.F32_BF16X3) as p:
+        info = p.info
+        assert info["num_s_materialized"] == a.R ** L and info["num_t_materialized"] == a.R ** L
+        dA, dB = to_dev(A), to_dev(B)
+        C = p.run_stage(F.STAGE_FORM_S, dA, dB)
+        p.run_stage(F.STAGE_FORM_T, dA, dB, C)
+        lm, lk, ln = info["leaf_m"], info["leaf_k"], info["leaf_n"]
+        for leaf in range(a.R ** L):
+            loc, off, row, col, ld, alpha = p.operand(0, leaf)
+            assert loc == F.LOC_WORKSPACE and alpha == 1.0 and ld % 8 == 0 and ld >= lk
+            eh, el = bf16x3.split(S[leaf].astype(np.float32))
+            hi = ws_read(p, off, lm, lk, ld, np.uint16)
+            lo = ws_read(p, off + lm * ld, lm, lk, ld, np.uint16)
+            bad_h = np.argwhere(hi != _bf16_bits(eh))
+            bad_l = np.argwhere(lo != _bf16_bits(el))
+            assert len(bad_h) == 0 and len(bad_l) == 0, (
+                "S", leaf, len(bad_h), len(bad_l), bad_h[:4].tolist(), bad_l[:4].tolist(),
+                S[leaf].flat[:3].tolist(), hi.flat[:3].tolist(), _bf16_bits(eh).flat[:3].tolist())
+            loc, off, row, col, ld, alpha = p.operand(1, leaf)
+            assert loc == F.LOC_WORKSPACE and alpha == 1.0 and ld == 8 * ln
+            groups = (lk + 7) // 8
+            th, tl = bf16x3.split(T[leaf].astype(np.float32))
+            raw_h = ws_read(p, off, groups, ld, ld, np.uint16).reshape(groups, ln, 8)
+            raw_l = ws_read(p, off + groups * ld, groups, ld, ld, np.uint16).reshape(groups, ln, 8)
+            # element (kk, nn) of a plane is at group kk // 8, column nn, slot kk % 8
+            got_h = raw_h.transpose(0, 2, 1).reshape(groups * 8, ln)[:lk]
+            got_l = raw_l.transpose(0, 2, 1).reshape(groups * 8, ln)[:lk]
+            assert np.array_equal(got_h, _bf16_bits(th)) and np.array_equal(got_l, _bf16_bits(tl)), ("T", leaf)

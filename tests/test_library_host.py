@@ -168,3 +168,23 @@ def test_host_only_plan_cannot_run():
     lib.fmm_multiply.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p, ctypes.c_int64] * 3 + [ctypes.c_void_p]
     lib.fmm_multiply.restype = ctypes.c_int
     assert lib.fmm_multiply(p._p, 1, 64, 2, 64, 3, 64, None) == 1
+
+
+@pytest.mark.parametrize("name,L", [("strassen_222_7", 1), ("strassen_222_7", 2), ("fmm_424_26", 2)])
+def test_bf16x3_leaf_operands_are_split_not_viewed(name, L):
+    """On the BF16x3 path every leaf operand is written as hi / lo bfloat16
+    planes (4 bytes per element, like the FP32 value it replaces): no views of
+    A or B, S planes row-major with rows padded to 8, T planes in k-octets."""
+    a = algorithms.get(name)
+    m, k, n = a.M ** L * 40, a.K ** L * 33, a.N ** L * 24
+    p = F.Plan(name, m, k, n, L, dtype=F.F32_BF16X3, host_only=True)
+    i = p.info
+    assert i["num_s_materialized"] == a.R ** L and i["num_t_materialized"] == a.R ** L
+    for leaf in range(a.R ** L):
+        loc, off, row, col, ld, alpha = p.operand(0, leaf)
+        assert loc == F.LOC_WORKSPACE and ld == 40 and alpha == 1.0  # round_up(33, 8)
+        loc, off, row, col, ld, alpha = p.operand(1, leaf)
+        assert loc == F.LOC_WORKSPACE and ld == 8 * 24 and alpha == 1.0
+    # the plain FP32 path keeps its views
+    q = F.Plan(name, m, k, n, L, dtype=F.F32, host_only=True).info
+    assert q["num_s_materialized"] < a.R ** L

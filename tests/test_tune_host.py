@@ -130,7 +130,7 @@ def test_recorded_choice_overrides_the_model(tmp_path):
 
 
 @pytest.mark.parametrize("fuse", ["1", "2"])
-@pytest.mark.parametrize("dtype", [F.F64, F.F32])
+@pytest.mark.parametrize("dtype", [F.F64, F.F32, F.F32_BF16X3])
 def test_model_summary_equals_the_full_plan(fuse, dtype, monkeypatch):
     """The model prices candidates from a closed-form summary of the plan
     (no R^L descriptors).  Its workspace and addition bytes must equal what
