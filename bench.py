@@ -74,7 +74,7 @@ def main():
     ap.add_argument("--arena-gb", type=float, default=96.0, help="serving: workspace arena (GB)")
     ap.add_argument("--max-batch", type=int, default=8)
     ap.add_argument("--max-inflight", type=int, default=2)
-    ap.add_argument("--sweep", default="square", choices=["square", "rect", "bf16x3"])
+    ap.add_argument("--sweep", default="square", choices=["square", "rect", "bf16x3", "latency"])
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -310,6 +310,31 @@ def run_sweep(args):
                                  for c in t["candidates"]]})
             del A, B, C
             torch.cuda.empty_cache()
+    elif args.sweep == "latency":
+        # config 1: 512^3 FP64 Strassen one level is launch-bound; per-call wall
+        # latency (enqueue + completion), eager vs graph replay vs classical
+        n = 512
+        A, B, C = operands(n, n, n, torch.float64)
+
+        def lat(fn, reps=300):
+            for _ in range(20):
+                fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) * 1e3)
+            ts.sort()
+            return {"p50_ms": ts[len(ts) // 2], "p99_ms": ts[int(len(ts) * 0.99)], "min_ms": ts[0]}
+
+        emit({"shape": [n, n, n], "alg": "classical", "levels": 0, **lat(lambda: F.gemm(A, B, C))})
+        for graph in (False, True):
+            p = F.Plan("strassen_222_7", n, n, n, 1, F.F64, use_graph=graph)
+            emit({"shape": [n, n, n], "alg": "strassen_222_7", "levels": 1, "graph": graph,
+                  **lat(lambda: p.multiply(A, B, C))})
+            p.close()
     else:
         for n in (8192, 16384):
             A, B, C = operands(n, n, n, torch.float32)
