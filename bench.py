@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
 HBM_PEAK_GBS = 8000.0
 
 
@@ -63,8 +64,11 @@ def main():
     ap.add_argument("--fuse", type=int, default=0, help="levels per addition pass (0 = library default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB device copy first (reference dispatch for HBM counters)")
-    ap.add_argument("--dtype", default="f64", choices=["f64"])
-    ap.add_argument("--cpu-rows", type=int, default=32, help="rows of the oracle CPU baseline sample")
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32", "bf16x3"],
+                    help="f64: uniform[-1,1) FP64 operands; f32 / bf16x3: FP32 normal(0,1) operands with 10%% "
+                         "of the rows of A and B scaled by 1e3, plain FP32 or BF16x3 leaves")
+    ap.add_argument("--cpu-rows", type=int, default=384,
+                    help="rows of the oracle CPU baseline sample (about 10 s of CPU work at 16384)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="multiply", choices=["multiply", "serving", "sweep"],
                     help="multiply: the one-line hot-path benchmark (default); serving: the request "
@@ -95,11 +99,17 @@ def main():
         return run_sweep(args)
     n = args.n
     m = k = n
-    log(f"[bench] generating {m}x{k} and {k}x{n} FP64 operands")
-    A, B = fmm_inputs.operands(0, m, k, n, "uniform")
+    dt = {"f64": F.F64, "f32": F.F32, "bf16x3": F.F32_BF16X3}[args.dtype]
+    elt = torch.float64 if dt == F.F64 else torch.float32
+    if dt == F.F64:
+        log(f"[bench] generating {m}x{k} and {k}x{n} FP64 operands")
+        A, B = fmm_inputs.operands(0, m, k, n, "uniform")
+    else:
+        log(f"[bench] generating {m}x{k} and {k}x{n} FP32 operands (row-scaled normal)")
+        A, B = fmm_inputs.operands(0, m, k, n, "normal_rowscaled", np.float32)
     dA = torch.from_numpy(A).to(dev)
     dB = torch.from_numpy(B).to(dev)
-    dC = torch.empty((m, n), dtype=torch.float64, device=dev)
+    dC = torch.empty((m, n), dtype=elt, device=dev)
     stream = torch.cuda.current_stream()
 
     if args.calibrate_copy:
@@ -110,7 +120,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    plan = F.Plan(args.alg, m, k, n, args.levels, F.F64, fuse_levels=args.fuse)
+    plan = F.Plan(args.alg, m, k, n, args.levels, dt, fuse_levels=args.fuse)
     info = plan.info
     log(f"[bench] plan {args.alg} L={args.levels}: leaf {info['leaf_m']}x{info['leaf_k']}x{info['leaf_n']}"
         f" x{info['num_leaves']}, workspace {info['workspace_bytes'] / 2**30:.2f} GiB")
@@ -132,19 +142,26 @@ def main():
     log(f"[bench] fast: {ms_per_step:.3f} ms/step, {eff_tflops:.2f} effective TFLOP/s, stages {stage_ms}")
 
     # same-GPU classical baseline: the same MFMA kernel on the one full problem
-    for _ in range(2):
-        F.gemm(dA, dB, dC)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    csteps = max(3, min(args.steps, 5))
-    ev0.record(stream)
-    for _ in range(csteps):
-        F.gemm(dA, dB, dC)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    classical_ms = ev0.elapsed_time(ev1) / csteps
-    classical_tflops = 2.0 * m * k * n / (classical_ms * 1e-3) / 1e12
+    def classical_rate(gdt):
+        for _ in range(2):
+            F.gemm(dA, dB, dC, dtype=gdt)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        csteps = max(3, min(args.steps, 5))
+        ev0.record(stream)
+        for _ in range(csteps):
+            F.gemm(dA, dB, dC, dtype=gdt)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        cms = ev0.elapsed_time(ev1) / csteps
+        return cms, 2.0 * m * k * n / (cms * 1e-3) / 1e12
+
+    classical_ms, classical_tflops = classical_rate(dt)
     log(f"[bench] classical MFMA GEMM: {classical_ms:.3f} ms, {classical_tflops:.2f} TFLOP/s")
+    plain_fp32 = None
+    if dt == F.F32_BF16X3:
+        plain_fp32 = round(classical_rate(F.F32)[1], 3)
+        log(f"[bench] plain FP32 classical MFMA GEMM: {plain_fp32} TFLOP/s")
 
     # error on sampled rows + CPU baseline (the oracle on those rows)
     plan.multiply(dA, dB, dC)
@@ -171,7 +188,18 @@ def main():
 
     leaf_ms = stage_ms[F.STAGE_LEAF]
     leaf_tflops = info["leaf_flops"] / (leaf_ms * 1e-3) / 1e12
-    traffic = traffic_from_profile("gemm_f64")
+    if dt == F.F64:
+        kernel, peak, tag = "gemm_kernel<double>", FP64_PEAK_TFLOPS, "gemm_f64"
+    elif dt == F.F32:
+        kernel, peak, tag = "gemm_kernel<float>", FP32_PEAK_TFLOPS, "gemm_f32"
+    else:
+        # three bf16 products per FP32 product, priced at the bf16 matrix peak
+        kernel, peak, tag = "gemm_bf16x3_kernel", BF16_PEAK_TFLOPS, "gemm_bf16x3"
+        leaf_tflops *= 3
+    traffic = traffic_from_profile(tag)
+    workload = (f"FP64 square {m}x{k}x{n}, uniform[-1,1)" if dt == F.F64 else
+                f"FP32 square {m}x{k}x{n}, normal(0,1) with 10% of rows of A and B x1e3, "
+                f"{'BF16x3' if dt == F.F32_BF16X3 else 'plain FP32'} leaves")
     out = {
         "metric": "effective TFLOP/s (2mkn/t) vs classical GEMM at fixed error; p50/p99 latency",
         "value": round(eff_tflops, 3),
@@ -183,19 +211,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": f"FP64 square {m}x{k}x{n}, uniform[-1,1), {args.alg} at {args.levels} levels",
+        "config": {"workload": f"{workload}, {args.alg} at {args.levels} levels",
                    "m": m, "k": k, "n": n, "alg": args.alg, "levels": args.levels,
                    "fuse_levels": info["fuse_levels"]},
         "classical_same_gpu_tflops": round(classical_tflops, 3),
+        "classical_plain_fp32_tflops": plain_fp32,
         "speedup_vs_classical": round(eff_tflops / classical_tflops, 4),
         "error_relF_sampled_rows": err,
         "stage_ms": {"form_s": stage_ms[0], "form_t": stage_ms[1], "leaf_gemm": stage_ms[2],
                      "combine": stage_ms[3]},
-        "roofline": {"bound": "mfma", "kernel": "gemm_kernel<double>",
-                     "achieved": round(leaf_tflops, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(leaf_tflops / FP64_PEAK_TFLOPS, 4), "traffic": traffic},
+        "roofline": {"bound": "mfma", "kernel": kernel,
+                     "achieved": round(leaf_tflops, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(leaf_tflops / peak, 4), "traffic": traffic},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
