@@ -108,18 +108,20 @@ def _bf16_bits(x32):
     return (np.ascontiguousarray(x32, dtype=np.float32).view(np.uint32) >> 16).astype(np.uint16)
 
 
-@pytest.mark.parametrize("alg,L", [("strassen_222_7", 1), ("strassen_222_7", 2), ("fmm_424_26", 1),
-                                   ("fmm_333_23", 1), ("fmm_423_20", 2)])
-def test_split_leaf_operands_bit_exact(F, alg, L):
+@pytest.mark.parametrize("alg,L,kmul", [("strassen_222_7", 1, 9), ("strassen_222_7", 2, 9), ("fmm_424_26", 1, 9),
+                                        ("fmm_333_23", 1, 9), ("fmm_423_20", 2, 9), ("strassen_222_7", 1, 16),
+                                        ("strassen_222_7", 2, 12), ("fmm_424_26", 1, 20)])
+def test_split_leaf_operands_bit_exact(F, alg, L, kmul):
     """On the BF16x3 path the formation kernels write every leaf operand as
     hi / lo bfloat16 planes: S row-major, T in k-octets (8 consecutive k of a
     column together).  Both planes must equal the split of the oracle's chain
     (binary64, ascending index, level by level) rounded once to FP32, bit for
-    bit; leaf k = 9 exercises a partial octet."""
+    bit; leaf k = 9 exercises a partial octet, leaf k a multiple of 4 the
+    coarsened S writer."""
     from oracle import recursive
     from gpu_util import ws_read
     a = algorithms.get(alg)
-    m, k, n = a.M ** L * 5, a.K ** L * 9, a.N ** L * 6
+    m, k, n = a.M ** L * 5, a.K ** L * kmul, a.N ** L * 6
     say(f"case split operands {alg} L={L} {m}x{k}x{n}")
     A, B = fmm_inputs.operands(15, m, k, n, "normal_rowscaled", np.float32)
     S = recursive.form_operands(a, L, A.astype(np.float64), "A")

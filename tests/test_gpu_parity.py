@@ -130,16 +130,19 @@ def _leaf_operand(F, p, side, leaf, A, B, dtype):
     return loc, off, row, col, ld, alpha
 
 
-@pytest.mark.parametrize("alg,L,fuse", [("strassen_222_7", 1, "1"), ("strassen_222_7", 2, "2"),
-                                        ("strassen_222_7", 3, "2"), ("fmm_424_26", 2, "1"),
-                                        ("fmm_333_23", 2, "2"), ("fmm_423_20", 1, "1")])
-def test_operand_formation_bit_exact(F, alg, L, fuse, monkeypatch):
+@pytest.mark.parametrize("alg,L,fuse,mult", [("strassen_222_7", 1, "1", 1), ("strassen_222_7", 2, "2", 1),
+                                             ("strassen_222_7", 3, "2", 1), ("fmm_424_26", 2, "1", 1),
+                                             ("fmm_333_23", 2, "2", 1), ("fmm_423_20", 1, "1", 1),
+                                             ("strassen_222_7", 1, "1", 8), ("strassen_222_7", 2, "2", 8),
+                                             ("fmm_424_26", 2, "1", 8), ("fmm_333_23", 1, "1", 8)])
+def test_operand_formation_bit_exact(F, alg, L, fuse, mult, monkeypatch):
     """Every leaf operand S_rho, T_rho produced by the formation kernels equals
     the oracle's chain (ascending index, level by level) bit for bit; views
-    equal alpha times the viewed block."""
+    equal alpha times the viewed block.  mult = 8 makes every block width a
+    multiple of 4 with 16-byte aligned rows (the coarsened kernels)."""
     monkeypatch.setenv("FMM_FUSE", fuse)
     a = algorithms.get(alg)
-    m, k, n = a.M ** L * 5, a.K ** L * 4, a.N ** L * 6
+    m, k, n = a.M ** L * 5 * mult, a.K ** L * 4 * mult, a.N ** L * 6 * mult
     say(f"case form {alg} L={L} fuse={fuse} m={m} k={k} n={n}")
     A, B = fmm_inputs.operands(6, m, k, n, "uniform")
     S = recursive.form_operands(a, L, A, "A")
