@@ -30,25 +30,34 @@ namespace fmm {
 namespace {
 
 // Sustained rates of this library's kernels on MI355X at large sizes
-// (classical 16384^3 leaf GEMM; streaming addition kernels).
-constexpr double kRateF64 = 61e12;     // flop/s, FP64 MFMA leaf
-constexpr double kRateF32 = 106e12;    // flop/s, FP32 MFMA leaf
-constexpr double kRateBf16x3 = 242e12; // FP32-equivalent flop/s, BF16x3 leaf
-constexpr double kAddBw = 4.8e12;      // byte/s, formation / combination passes
+// (16384^3 leaf launches; streaming addition kernels).
+constexpr double kRateF64 = 65e12;          // flop/s, FP64 MFMA
+constexpr double kRateF32 = 110e12;         // flop/s, FP32 MFMA
+constexpr double kRateBf16x3Split = 300e12; // FP32-equivalent flop/s, BF16x3 on split leaf operands
+constexpr double kRateBf16x3 = 245e12;      // FP32-equivalent flop/s, BF16x3 splitting FP32 tiles
+constexpr double kAddBw = 4.8e12;           // byte/s, formation / combination passes
 constexpr double kLaunch = 6e-6;       // s per kernel launch on a busy stream
 constexpr double kFix = 32;            // per-tile fixed cost, in units of k
 constexpr int kSlots = 512;            // resident leaf workgroups (2 per compute unit)
 constexpr int64_t kMaxLeaves = 60000;  // candidates with more leaves are not offered
 
-double rate(int dtype) { return dtype == 0 ? kRateF64 : dtype == 1 ? kRateF32 : kRateBf16x3; }
+// Rate of group g of a plan: on the BF16x3 path the leaf group (the first
+// group of a recursive plan) reads split operands, the others FP32 ones.
+double rate(int dtype, bool split_leaf) {
+  if (dtype == 0) return kRateF64;
+  if (dtype == 1) return kRateF32;
+  return split_leaf ? kRateBf16x3Split : kRateBf16x3;
+}
 
 void predict(const PlanSummary& P, int dtype, Candidate& c) {
-  // leaf: tile-work units of every group, quantised to whole waves of the
-  // largest tile cost
+  // leaf: tile-work units of every group (scaled to the group's rate),
+  // quantised to whole waves of the largest tile cost
+  const double ref = rate(dtype, false);
   double units = 0, wmax = 0, tiles = 0;
-  for (const GemmGroup& g : P.groups) {
+  for (size_t i = 0; i < P.groups.size(); ++i) {
+    const GemmGroup& g = P.groups[i];
     const double t = (double)g.tiles_m * g.tiles_n * g.count;
-    const double w = (double)g.k + kFix;
+    const double w = ((double)g.k + kFix) * ref / rate(dtype, i == 0 && P.levels > 0);
     units += t * w;
     tiles += t;
     wmax = std::max(wmax, w);
@@ -56,7 +65,7 @@ void predict(const PlanSummary& P, int dtype, Candidate& c) {
   double leaf_s = 0;
   if (tiles > 0) {
     const double waves = std::ceil(units / (kSlots * wmax));
-    const double per_unit = 2.0 * kTileM * kTileN / (rate(dtype) / kSlots);
+    const double per_unit = 2.0 * kTileM * kTileN / (ref / kSlots);
     leaf_s = waves * wmax * per_unit;
   }
   const double add_s = P.add_bytes / kAddBw;
