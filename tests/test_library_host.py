@@ -188,3 +188,39 @@ def test_bf16x3_leaf_operands_are_split_not_viewed(name, L):
     # the plain FP32 path keeps its views
     q = F.Plan(name, m, k, n, L, dtype=F.F32, host_only=True).info
     assert q["num_s_materialized"] < a.R ** L
+
+
+def test_argument_errors_before_any_device_call():
+    """Entry points reject bad arguments with FMM_EINVAL (1) before touching a
+    device; NULL handles are accepted where the header says so."""
+    lib = F._lib
+    vp = ctypes.c_void_p
+    # batched multiply: zero requests is a no-op, a negative count an error
+    assert lib.fmm_multiply_batched(None, None, None, None, None, None, None, 0, None) == 0
+    assert lib.fmm_multiply_batched(None, None, None, None, None, None, None, -1, None) == 1
+    # binding memory to a plan that was not made with defer_device_memory
+    p = F.Plan("strassen_222_7", 64, 64, 64, 1, host_only=True)
+    assert lib.fmm_plan_bind(p._p, vp(1 << 20), 1 << 30, None) == 1
+    assert lib.fmm_plan_device_bytes(None) == 0
+    # ranking: negative capacity is an error, zero capacity returns nothing
+    cnt = ctypes.c_int(-1)
+    assert lib.fmm_rank_candidates(64, 64, 64, 0, None, 0, None, -1, ctypes.byref(cnt)) == 1
+    assert lib.fmm_rank_candidates(64, 64, 64, 0, None, 0, None, 0, ctypes.byref(cnt)) == 0 and cnt.value == 0
+    # server options
+    srv = vp()
+    for arena, batch, inflight in ((0, 8, 2), (1 << 20, 0, 2), (1 << 20, 65, 2), (1 << 20, 8, 0)):
+        opts = F._ServerOptions(arena, batch, inflight, 0)
+        assert lib.fmm_server_create(ctypes.byref(srv), ctypes.byref(opts), None) == 1
+    assert lib.fmm_server_create(ctypes.byref(srv), None, None) == 1
+    assert lib.fmm_server_submit(None, None, None) == 1
+    n = ctypes.c_int(-1)
+    assert lib.fmm_server_progress(None, 0, None, 0, ctypes.byref(n)) == 1 and n.value == 0
+    assert lib.fmm_server_pending(None) == 0
+    assert lib.fmm_server_destroy(None) == 0
+    # recorded choices must name a valid plan
+    from paper_1409_2908_amd import autotune
+    for args in ((-1, 8, 8, 0, "strassen_222_7", 1, 0), (64, 64, 64, 0, "strassen_222_7", 1, 3),
+                 (64, 64, 64, 5, "strassen_222_7", 1, 0), (64, 64, 64, 0, "strassen_222_7", -1, 0)):
+        with pytest.raises(F.FmmError) as e:
+            autotune.record(*args)
+        assert e.value.code == 1
