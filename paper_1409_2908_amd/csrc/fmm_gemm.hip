@@ -32,6 +32,8 @@
 // (8 tile rows per group) and share A and B panels in that XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fmm_device.h"
 #include "fmm_gemm_common.h"
 #include "fmm_launch.h"
@@ -152,32 +154,75 @@ gemm_kernel(GemmArgs args) {
     };
 
     const int64_t nk = (K + GBK - 1) / GBK;
-    if (nk > 0) {
-      gload(0);
-      lstore(0);
-    }
-    __syncthreads();
-    for (int64_t kt = 0; kt < nk; ++kt) {
-      const int cur = (int)(kt & 1);
-      if (kt + 1 < nk) gload((kt + 1) * GBK);
+    if constexpr (std::is_same_v<T, float>) {
+      // FP32: fragment registers for the four sub-steps of a K step, and the
+      // barrier between the MFMAs of sub-steps 2 and 3.  Every read of the
+      // current buffer is issued before it and the next buffer has been
+      // written before it; after it the next step's first fragments are read
+      // while sub-step 3's MFMAs run.  (Measured +5% over the schedule below
+      // for FP32, -2% for FP64, whose longer MFMAs already hide the reads.)
+      T af[KPL][TI], bf[KPL][TJ];
+      auto rd = [&](int buf, int kk) {
 #pragma unroll
-      for (int kk = 0; kk < KPL; ++kk) {
-        T af[TI], bf[TJ];
+        for (int i = 0; i < TI; ++i) af[kk][i] = As[buf][wm * WTM + i * 16 + li][lg * KPL + kk];
 #pragma unroll
-        for (int i = 0; i < TI; ++i) af[i] = As[cur][wm * WTM + i * 16 + li][lg * KPL + kk];
-#pragma unroll
-        for (int j = 0; j < TJ; ++j) bf[j] = Bs[cur][lg * KPL + kk][wn * WTN + j * 16 + li];
+        for (int j = 0; j < TJ; ++j) bf[kk][j] = Bs[buf][lg * KPL + kk][wn * WTN + j * 16 + li];
+      };
+      auto mma = [&](int kk) {
 #pragma unroll
         for (int i = 0; i < TI; ++i)
 #pragma unroll
-          for (int j = 0; j < TJ; ++j) acc[i][j] = MF::op(af[i], bf[j], acc[i][j]);
-        // The other buffer's readers all passed the previous barrier, so the
-        // next step's tile can be written now; doing it before the last
-        // sub-step hides the LDS writes behind its MFMAs (the loads issued at
-        // the top of the step have had three sub-steps to land).
-        if (kk == KPL - 2 && kt + 1 < nk) lstore(cur ^ 1);
+          for (int j = 0; j < TJ; ++j) acc[i][j] = MF::op(af[kk][i], bf[kk][j], acc[i][j]);
+      };
+      if (nk > 0) {
+        gload(0);
+        lstore(0);
       }
       __syncthreads();
+      if (nk > 0) rd(0, 0);
+      for (int64_t kt = 0; kt < nk; ++kt) {
+        const int cur = (int)(kt & 1);
+        const bool more = kt + 1 < nk;
+        if (more) gload((kt + 1) * GBK);
+        rd(cur, 1);
+        mma(0);
+        rd(cur, 2);
+        rd(cur, 3);
+        mma(1);
+        if (more) lstore(cur ^ 1);
+        mma(2);
+        __syncthreads();
+        if (more) rd(cur ^ 1, 0);
+        mma(3);
+      }
+    } else {
+      if (nk > 0) {
+        gload(0);
+        lstore(0);
+      }
+      __syncthreads();
+      for (int64_t kt = 0; kt < nk; ++kt) {
+        const int cur = (int)(kt & 1);
+        if (kt + 1 < nk) gload((kt + 1) * GBK);
+#pragma unroll
+        for (int kk = 0; kk < KPL; ++kk) {
+          T af[TI], bf[TJ];
+#pragma unroll
+          for (int i = 0; i < TI; ++i) af[i] = As[cur][wm * WTM + i * 16 + li][lg * KPL + kk];
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) bf[j] = Bs[cur][lg * KPL + kk][wn * WTN + j * 16 + li];
+#pragma unroll
+          for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) acc[i][j] = MF::op(af[i], bf[j], acc[i][j]);
+          // The other buffer's readers all passed the previous barrier, so the
+          // next step's tile can be written now; doing it before the last
+          // sub-step hides the LDS writes behind its MFMAs (the loads issued at
+          // the top of the step have had three sub-steps to land).
+          if (kk == KPL - 2 && kt + 1 < nk) lstore(cur ^ 1);
+        }
+        __syncthreads();
+      }
     }
 
     const __amdgpu_buffer_rsrc_t sc = make_rsrc(C);
