@@ -4,10 +4,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -34,15 +36,15 @@ fmm_status hip_fail(hipError_t e, const char* what) {
 }
 
 int num_cus(int device) {
-  static int cached[64] = {0};
+  static std::atomic<int> cached[64];  // 0 = not queried yet
   if (device < 0 || device >= 64) return 256;
-  if (!cached[device]) {
-    int v = 0;
+  int v = cached[device].load(std::memory_order_relaxed);
+  if (!v) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || v <= 0)
       v = 256;
-    cached[device] = v;
+    cached[device].store(v, std::memory_order_relaxed);
   }
-  return cached[device];
+  return v;
 }
 
 // Exact Brent check of one table (Equation (2) against the tensor of
@@ -66,17 +68,17 @@ bool brent_ok(const fmm::AlgInfo& a, std::string* why) {
 }
 
 fmm_status check_tables_once() {
-  static int state = 0;  // 0 unknown, 1 ok, 2 bad
+  static std::once_flag once;
+  static bool ok = true;
   static std::string why;
-  if (state == 0) {
-    state = 1;
+  std::call_once(once, [] {
     for (int i = 0; i < fmm::kNumAlgorithms; ++i)
       if (!brent_ok(fmm::alg_info(i), &why)) {
-        state = 2;
+        ok = false;
         break;
       }
-  }
-  return state == 1 ? FMM_OK : fail(FMM_EALG, why);
+  });
+  return ok ? FMM_OK : fail(FMM_EALG, why);
 }
 
 size_t elt_size(int elt) { return elt == fmm::ELT_F64 ? 8 : 4; }

@@ -32,6 +32,7 @@
 // (8 tile rows per group) and share A and B panels in that XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <type_traits>
 
 #include "fmm_device.h"
@@ -241,13 +242,13 @@ gemm_kernel(GemmArgs args) {
 
 template <typename T>
 static int blocks_per_cu() {
-  static int cached = 0;
-  if (!cached) {
-    int b = 0;
+  static std::atomic<int> cached{0};
+  int b = cached.load(std::memory_order_relaxed);
+  if (!b) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, gemm_kernel<T>, GNT, 0) != hipSuccess || b < 1) b = 1;
-    cached = b;
+    cached.store(b, std::memory_order_relaxed);
   }
-  return cached;
+  return b;
 }
 
 hipError_t launch_gemm(const GemmArgs& a, int dtype, int num_cus, hipStream_t s) {

@@ -23,6 +23,8 @@
 // edge are dropped).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "fmm_gemm_common.h"
 #include "fmm_launch.h"
 
@@ -348,11 +350,12 @@ gemm_bf16x3_kernel(GemmArgs args) {
 
 hipError_t launch_gemm_bf16x3(const GemmArgs& a, int num_cus, hipStream_t s) {
   if (a.total_tiles <= 0) return hipSuccess;
-  static int per_cu = 0;
+  static std::atomic<int> cached{0};
+  int per_cu = cached.load(std::memory_order_relaxed);
   if (!per_cu) {
-    int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, gemm_bf16x3_kernel, XNT, 0) != hipSuccess || b < 1) b = 1;
-    per_cu = b;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gemm_bf16x3_kernel, XNT, 0) != hipSuccess || per_cu < 1)
+      per_cu = 1;
+    cached.store(per_cu, std::memory_order_relaxed);
   }
   int64_t G = (int64_t)per_cu * num_cus;
   const int64_t want = (a.total_tiles + 7) / 8 * 8;
