@@ -149,3 +149,31 @@ def test_model_summary_equals_the_full_plan(fuse, dtype, monkeypatch):
                 assert abs(c["add_ms"] - i["add_bytes"] / 4.8e12 * 1e3) <= 1e-12 * max(1.0, c["add_ms"])
                 checked += 1
     assert checked > 60
+
+
+def test_concurrent_planning_and_ranking_agree_with_serial():
+    """Planning, ranking and recording from several threads at once (ctypes
+    releases the interpreter lock during library calls) give the same answers
+    as one thread: the library's shared state is the tuned-choice table and
+    one-time caches."""
+    import concurrent.futures as cf
+    from paper_1409_2908_amd import autotune
+    shapes = [(4096 + 17 * i, 3000 + 29 * i, 5000 - 31 * i) for i in range(24)]
+
+    def work(sh):
+        top = F.rank_candidates(*sh, F.F64)[0]
+        p = F.Plan("auto", *sh, -1, host_only=True)
+        autotune.record(*sh, F.F32, "strassen_222_7", 1)
+        q = F.Plan("auto", *sh, -1, dtype=F.F32, host_only=True)
+        return (top["alg"], top["levels"]), (p.alg, p.levels), (q.alg, q.levels), p.workspace_bytes
+
+    try:
+        serial = [work(sh) for sh in shapes]
+        autotune.clear()
+        with cf.ThreadPoolExecutor(max_workers=8) as ex:
+            parallel = list(ex.map(work, shapes))
+        assert parallel == serial
+        for top, picked, rec, _ in parallel:
+            assert top == picked and rec == ("strassen_222_7", 1)
+    finally:
+        autotune.clear()
