@@ -295,33 +295,60 @@ __device__ __forceinline__ void bf16x3_tile(Bf16x3Smem& sm, const float* A, cons
   };
 
   const int64_t nk = (K + XBK - 1) / XBK;
+  // Same schedule as bf16x3_tile_split: barrier after the third column block,
+  // the next step's fragments read under the last block's MFMAs.
+  bf8_t ah[4], al[4], bh[2], bl[2];
+  auto rd_a = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ah[i] = *(const bf8_t*)&sm.a_hi[buf][wm * 64 + i * 16 + li][8 * lg];
+      al[i] = *(const bf8_t*)&sm.a_lo[buf][wm * 64 + i * 16 + li][8 * lg];
+    }
+  };
+  auto rd_b = [&](int buf, int j) {
+    bh[j & 1] = *(const bf8_t*)&sm.b_hi[buf][wn * 64 + j * 16 + li][8 * lg];
+    bl[j & 1] = *(const bf8_t*)&sm.b_lo[buf][wn * 64 + j * 16 + li][8 * lg];
+  };
+  auto mma = [&](int j) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j & 1], acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j & 1], acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j & 1], acc[i][j], 0, 0, 0);
+    }
+  };
   if (nk > 0) {
     gload(0);
     lstore(0);
   }
   __syncthreads();
+  if (nk > 0) {
+    rd_a(0);
+    rd_b(0, 0);
+  }
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int cur = (int)(kt & 1);
-    if (kt + 1 < nk) gload((kt + 1) * XBK);
-    bf8_t ah[4], al[4];
+    const bool more = kt + 1 < nk;
+    if (more) gload((kt + 1) * XBK);
+    rd_b(cur, 1);
+    mma(0);
+    rd_b(cur, 2);
+    mma(1);
+    if (more) lstore(cur ^ 1);
+    rd_b(cur, 3);
+    mma(2);
+    __syncthreads();
+    if (more) rd_b(cur ^ 1, 0);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      ah[i] = *(const bf8_t*)&sm.a_hi[cur][wm * 64 + i * 16 + li][8 * lg];
-      al[i] = *(const bf8_t*)&sm.a_lo[cur][wm * 64 + i * 16 + li][8 * lg];
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const bf8_t bh = *(const bf8_t*)&sm.b_hi[cur][wn * 64 + j * 16 + li][8 * lg];
-      const bf8_t bl = *(const bf8_t*)&sm.b_lo[cur][wn * 64 + j * 16 + li][8 * lg];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+      acc[i][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[1], acc[i][3], 0, 0, 0);
+      acc[i][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[1], acc[i][3], 0, 0, 0);
+      acc[i][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[1], acc[i][3], 0, 0, 0);
+      if (more) {
+        ah[i] = *(const bf8_t*)&sm.a_hi[cur ^ 1][wm * 64 + i * 16 + li][8 * lg];
+        al[i] = *(const bf8_t*)&sm.a_lo[cur ^ 1][wm * 64 + i * 16 + li][8 * lg];
       }
     }
-    if (kt + 1 < nk) lstore(cur ^ 1);
-    __syncthreads();
   }
 
   const __amdgpu_buffer_rsrc_t sc = make_rsrc(C);
