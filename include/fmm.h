@@ -89,7 +89,8 @@ typedef struct {
 
 /* Options of fmm_plan_ex.  Zero-initialise, then set what you need. */
 typedef struct {
-    int fuse_levels;   /* 0: library default (2 for base cases with R <= 8, else 1);
+    int fuse_levels;   /* 0: library default (2, except 1 for FMM_F32_BF16X3 plans of base
+                          cases with R > 8);
                           1 or 2: recursion levels per operand-formation / combination pass */
     int host_only;     /* non-zero: plan on the host only, as fmm_plan_host */
     int use_graph;     /* non-zero: fmm_multiply records its launches once into a HIP graph

@@ -9,8 +9,14 @@
 // the write-once variant's single output stream per store instruction.  A
 // wavefront covers 64 consecutive q, so every load and store instruction moves
 // 512 contiguous bytes (FP64).  Up to two recursion levels are fused per pass
-// (their Kronecker-product coefficients are applied level by level in
-// registers, top level first, which is the recursion's own order).
+// (their Kronecker-product coefficients are applied level by level, top level
+// first, which is the recursion's own order): in registers for narrow base
+// cases (R <= 8), and through LDS for wide ones, where a workgroup stages the
+// (BR*BC)^2 sources (formation) or the R^2 products (combination) of 64
+// positions once and its wavefronts share the level-one sums; the two-level
+// combination always takes the LDS path.  Every variant performs the same
+// roundings in the same order, so fused and one-level passes agree bit for
+// bit.
 #include <hip/hip_runtime.h>
 
 #include "fmm_device.h"
@@ -91,6 +97,102 @@ __global__ void __launch_bounds__(kAddTX * kAddTY) form_kernel(FormArgs a) {
   }
 }
 
+
+// Coefficients of one side as a device table with one row of NB integers per
+// output r, so a wave-uniform r reads its row with scalar loads.
+template <int ID, int SIDE>
+struct ColTable {
+  int c[Side<ID, SIDE>::R][Side<ID, SIDE>::NB];
+};
+
+template <int ID, int SIDE>
+constexpr ColTable<ID, SIDE> make_col_table() {
+  ColTable<ID, SIDE> t{};
+  for (int r = 0; r < Side<ID, SIDE>::R; ++r)
+    for (int i = 0; i < Side<ID, SIDE>::NB; ++i) t.c[r][i] = Side<ID, SIDE>::coef(i, r);
+  return t;
+}
+
+template <int ID, int SIDE>
+__constant__ ColTable<ID, SIDE> kColTable = make_col_table<ID, SIDE>();
+
+// Two levels of operand formation in one pass for wide base cases, staged
+// through LDS.  A workgroup owns 64 consecutive columns q of one row p of
+// the leaf-sized grid: it first loads the NB^2 source elements of those 64
+// positions into LDS (every load instruction of a wavefront reads 512
+// contiguous bytes and a thread has NB^2 / 4 loads in flight), then each
+// wavefront takes every fourth top-level output r1, forms the NB level-two
+// sums y[i2] = sum_i1 U[i1][r1] x[i1][i2] from LDS, and writes
+// S_{r1,r2} = sum_i2 U[i2][r2] y[i2] for every r2.  Sums run in ascending
+// index order from -0.0 with fused multiply-adds: with coefficients +-2^e the
+// first step returns c*x exactly and every later one rounds like the
+// corresponding add or subtract of the chain, so the results equal the
+// register kernel's bit for bit.
+template <int ID, int SIDE>
+__global__ void __launch_bounds__(256) form2_kernel(FormArgs a) {
+  using S = Side<ID, SIDE>;
+  constexpr int NB = S::NB, R = S::R, BR = S::BR, BC = S::BC, NIN = NB * NB;
+  __shared__ double xs[NIN][64];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t p = blockIdx.y;
+  const int g = blockIdx.z;
+  const bool valid = q < a.w;
+  const Ref src = a.groups[g];
+  int64_t ld;
+  const char* base = buf_ptr(a.bases, src, &ld);
+  const int64_t h = a.h, w = a.w;
+  // Branch-free loads, all in flight before the first LDS store: lanes past
+  // the last column read column w - 1 and store 0.
+  const int64_t qc = valid ? q : w - 1;
+  constexpr int NJ = (NIN + 3) / 4;
+  double v[NJ];
+  auto load_all = [&](auto tag) {
+    using T = decltype(tag);
+    const T* bp = (const T*)base + src.off;
+#pragma unroll
+    for (int k = 0; k < NJ; ++k) {
+      const int idx = wave + 4 * k < NIN ? wave + 4 * k : NIN - 1;
+      const int i1 = idx / NB, i2 = idx % NB;
+      const int a1 = i1 / BC, b1 = i1 % BC, a2 = i2 / BC, b2 = i2 % BC;
+      const int64_t row = src.row + (a1 * BR + a2) * h + p;
+      const int64_t col = src.col + (b1 * BC + b2) * w + qc;
+      v[k] = (double)bp[row * ld + col];
+    }
+  };
+  if (src.elt == ELT_F64) load_all(double{});
+  else load_all(float{});
+#pragma unroll
+  for (int k = 0; k < NJ; ++k)
+    if (wave + 4 * k < NIN) xs[wave + 4 * k][lane] = valid ? v[k] * src.alpha : 0.0;
+  __syncthreads();
+  if (!valid) return;
+  char* ws = (char*)a.bases.ptr[BUF_WS];
+  const int64_t* outs = a.outs + (int64_t)g * a.nout;
+  const int64_t pos = p * a.out_ld + q;
+  const ColTable<ID, SIDE>& tab = kColTable<ID, SIDE>;
+  for (int r1 = wave; r1 < R; r1 += 4) {
+    double y[NB];
+#pragma unroll
+    for (int i2 = 0; i2 < NB; ++i2) {
+      double acc = -0.0;
+#pragma unroll
+      for (int i1 = 0; i1 < NB; ++i1) {
+        const int c = tab.c[r1][i1];
+        if (c != 0) acc = __fma_rn((double)c, xs[i1 * NB + i2][lane], acc);
+      }
+      y[i2] = acc;
+    }
+    const int64_t* o = outs + r1 * R;
+    static_for<0, R>([&](auto r2c) {
+      constexpr int r2 = decltype(r2c)::value;
+      const int64_t off = o[r2];
+      if (off >= 0) store_out(ws, a.out_elt, off + pos, a.out_plane, chain_col<S, r2, 1, NB>(y));
+    });
+  }
+}
+
 // W-combination, one level: C_k = sum_r W[k][r] M_r at each position.
 template <int ID>
 __global__ void __launch_bounds__(kAddTX * kAddTY) combine1_kernel(CombineArgs a) {
@@ -124,55 +226,92 @@ __global__ void __launch_bounds__(kAddTX * kAddTY) combine1_kernel(CombineArgs a
   });
 }
 
-// W-combination, two levels fused.  A workgroup of MN wavefronts covers 64
-// consecutive positions; wavefront c2 owns the deeper-level output block c2
-// and accumulates the top-level outputs C_{c1,c2} for every c1 in registers.
-// For each top-level product r1 the workgroup stages the R products
-// M_{r1,r2} of its 64 positions in LDS (each element read from HBM once),
-// every wavefront forms Y_{r1,c2} = sum_r2 W[c2][r2] M_{r1,r2} from LDS, and
-// adds W[c1][r1] Y_{r1,c2} into its accumulators.  Sums run in ascending
-// index order starting from zero; with coefficients 0 or +-2^e each fused
-// multiply-add rounds exactly like the corresponding chain step.
 template <int ID>
-__global__ void __launch_bounds__(1024) combine2_kernel(CombineArgs a) {
+struct WTable {
+  int c[Comb<ID>::MN][Comb<ID>::R];
+};
+
+template <int ID>
+constexpr WTable<ID> make_w_table() {
+  WTable<ID> t{};
+  for (int k = 0; k < Comb<ID>::MN; ++k)
+    for (int r = 0; r < Comb<ID>::R; ++r) t.c[k][r] = Comb<ID>::coef(k, r);
+  return t;
+}
+
+template <int ID>
+__constant__ WTable<ID> kWTable = make_w_table<ID>();
+
+// W-combination, two levels fused, for wide base cases.  A workgroup of four
+// wavefronts owns 64 consecutive positions of one row; wavefront w owns the
+// top-level output blocks c1 = w, w+4, ... and accumulates C_{c1,c2} for
+// every deeper block c2 in registers.  The products are staged through LDS
+// RC top-level indices r1 at a time (R*RC*64 elements, every element read
+// from HBM once, RC*R/4 loads in flight per thread); from LDS each wavefront
+// forms Y_{r1,c2} = sum_r2 W[c2][r2] M_{r1,r2} for all c2 (compile-time
+// chains) and adds W[c1][r1] Y_{r1,c2}.  Same summation order as the
+// one-level passes, so the results are bitwise theirs.
+template <int ID>
+__global__ void __launch_bounds__(256) combine2_kernel(CombineArgs a) {
   using CB = Comb<ID>;
   constexpr int R = CB::R, MN = CB::MN, N = Alg<ID>::N, M = Alg<ID>::M;
-  __shared__ double sm[2][R][64];
+  constexpr int RC = 4, CPW = (MN + 3) / 4;
+  constexpr int NLD = RC * R * 64 / 256;  // loads per thread and stage
+  __shared__ double sm[RC * R][64];
   const int lane = threadIdx.x & 63;
-  const int c2 = threadIdx.x >> 6;  // wave-uniform
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t q = (int64_t)blockIdx.x * 64 + lane;
   const int64_t p = blockIdx.y;
   const int g = blockIdx.z;
   const char* ws = (const char*)a.bases.ptr[BUF_WS];
   const int64_t gbase = a.in_off[g] + p * a.in_ld;
-  // Accumulators start at -0.0 so that the first fused multiply-add returns
-  // exactly c*x, signed zeros included, like the first term of a chain.
-  double acc[MN];
+  const WTable<ID>& tab = kWTable<ID>;
+  double acc[CPW][MN];
 #pragma unroll
-  for (int c1 = 0; c1 < MN; ++c1) acc[c1] = -0.0;
-  auto stage = [&](int buf, int r1) {
-    for (int e = threadIdx.x; e < R * 64; e += MN * 64) {
-      const int r2 = e >> 6, l = e & 63;
+  for (int cc = 0; cc < CPW; ++cc)
+#pragma unroll
+    for (int c2 = 0; c2 < MN; ++c2) acc[cc][c2] = -0.0;
+  for (int r0 = 0; r0 < R; r0 += RC) {
+    double v[NLD];
+#pragma unroll
+    for (int j = 0; j < NLD; ++j) {
+      const int e = (int)threadIdx.x + 256 * j;
+      const int rr = e >> 6, l = e & 63;
       const int64_t qq = (int64_t)blockIdx.x * 64 + l;
-      double v = 0.0;
-      if (qq < a.w) v = load_elt(ws, a.in_elt, gbase + ((int64_t)r1 * R + r2) * a.in_stride + qq);
-      sm[buf][r2][l] = v;
-    }
-  };
-  stage(0, 0);
-  __syncthreads();
-  for (int r1 = 0; r1 < R; ++r1) {
-    const int cur = r1 & 1;
-    if (r1 + 1 < R) stage(cur ^ 1, r1 + 1);
-    double y = -0.0;
-    for (int r2 = 0; r2 < R; ++r2) {
-      const int c = a.wc[c2][r2];
-      if (c != 0) y = __fma_rn((double)c, sm[cur][r2][lane], y);
+      v[j] = (r0 * R + rr < R * R && qq < a.w)
+                 ? load_elt(ws, a.in_elt, gbase + (int64_t)(r0 * R + rr) * a.in_stride + qq)
+                 : 0.0;
     }
 #pragma unroll
-    for (int c1 = 0; c1 < MN; ++c1) {
-      const int c = a.wc[c1][r1];
-      if (c != 0) acc[c1] = __fma_rn((double)c, y, acc[c1]);
+    for (int j = 0; j < NLD; ++j) {
+      const int e = (int)threadIdx.x + 256 * j;
+      sm[e >> 6][e & 63] = v[j];
+    }
+    __syncthreads();
+    for (int j = 0; j < RC && r0 + j < R; ++j) {
+      const int r1 = r0 + j;
+      double y[MN];
+      static_for<0, MN>([&](auto c2c) {
+        constexpr int c2 = decltype(c2c)::value;
+        double t = -0.0;
+        static_for<0, R>([&](auto r2c) {
+          constexpr int r2 = decltype(r2c)::value;
+          constexpr int c = CB::coef(c2, r2);
+          if constexpr (c != 0) t = __fma_rn((double)c, sm[j * R + r2][lane], t);
+        });
+        y[c2] = t;
+      });
+#pragma unroll
+      for (int cc = 0; cc < CPW; ++cc) {
+        const int c1 = wave + 4 * cc;
+        if (c1 < MN) {
+          const int c = tab.c[c1][r1];
+          if (c != 0) {
+#pragma unroll
+            for (int c2 = 0; c2 < MN; ++c2) acc[cc][c2] = __fma_rn((double)c, y[c2], acc[cc][c2]);
+          }
+        }
+      }
     }
     __syncthreads();
   }
@@ -182,17 +321,22 @@ __global__ void __launch_bounds__(1024) combine2_kernel(CombineArgs a) {
   char* ob = buf_ptr(a.bases, out, &ld);
   int64_t pld = 0;
   const char* pb = a.has_p ? buf_ptr(a.bases, a.p, &pld) : nullptr;
-  const int a2 = c2 / N, cc2 = c2 % N;
 #pragma unroll
-  for (int c1 = 0; c1 < MN; ++c1) {
+  for (int cc = 0; cc < CPW; ++cc) {
+    const int c1 = wave + 4 * cc;
+    if (c1 >= MN) continue;
     const int a1 = c1 / N, cc1 = c1 % N;
-    const int64_t row = (int64_t)(a1 * M + a2) * a.h + p;
-    const int64_t col = (int64_t)(cc1 * N + cc2) * a.w + q;
-    double v = acc[c1];
-    if (a.has_p) v = __dadd_rn(v, load_elt(pb, a.p.elt, a.p.off + row * pld + col));
-    const int64_t idx = out.off + (out.row + row) * ld + out.col + col;
-    if (out.elt == ELT_F64) ((double*)ob)[idx] = v;
-    else ((float*)ob)[idx] = (float)v;
+#pragma unroll
+    for (int c2 = 0; c2 < MN; ++c2) {
+      const int a2 = c2 / N, cc2 = c2 % N;
+      const int64_t row = (int64_t)(a1 * M + a2) * a.h + p;
+      const int64_t col = (int64_t)(cc1 * N + cc2) * a.w + q;
+      double v = acc[cc][c2];
+      if (a.has_p) v = __dadd_rn(v, load_elt(pb, a.p.elt, a.p.off + row * pld + col));
+      const int64_t idx = out.off + (out.row + row) * ld + out.col + col;
+      if (out.elt == ELT_F64) ((double*)ob)[idx] = v;
+      else ((float*)ob)[idx] = (float)v;
+    }
   }
 }
 
@@ -209,13 +353,25 @@ static hipError_t launch_form_id(const FormArgs& a, int side, int lv, int ngroup
     else return hipErrorInvalidValue;
     return hipGetLastError();
   }
+  // Two fused levels of a wide base case go through LDS, except split T
+  // operands (k-octet layout), which keep the register kernel's 8 x 8 mapping.
+  if (lv == 2 && Alg<ID>::R > 8 && !(side == 1 && a.out_elt == ELT_BF16X2)) {
+    dim3 g2((unsigned)((a.w + 63) / 64), (unsigned)a.h, (unsigned)ngroups);
+    if (side == 0) hipLaunchKernelGGL((form2_kernel<ID, 0>), g2, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((form2_kernel<ID, 1>), g2, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((a.w + kAddTX - 1) / kAddTX), (unsigned)((a.h + kAddTY - 1) / kAddTY),
             (unsigned)ngroups);
   if (side == 0 && lv == 1) hipLaunchKernelGGL((form_kernel<ID, 0, 1>), grid, block, 0, s, a);
-  else if (side == 0 && lv == 2) hipLaunchKernelGGL((form_kernel<ID, 0, 2>), grid, block, 0, s, a);
   else if (side == 1 && lv == 1) hipLaunchKernelGGL((form_kernel<ID, 1, 1>), grid, block, 0, s, a);
-  else if (side == 1 && lv == 2) hipLaunchKernelGGL((form_kernel<ID, 1, 2>), grid, block, 0, s, a);
-  else return hipErrorInvalidValue;
+  else if constexpr (Alg<ID>::R <= 8) {
+    if (side == 0 && lv == 2) hipLaunchKernelGGL((form_kernel<ID, 0, 2>), grid, block, 0, s, a);
+    else if (side == 1 && lv == 2) hipLaunchKernelGGL((form_kernel<ID, 1, 2>), grid, block, 0, s, a);
+    else return hipErrorInvalidValue;
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -240,10 +396,8 @@ static hipError_t launch_combine_id(const CombineArgs& a, int lv, int ngroups, h
               (unsigned)ngroups);
     hipLaunchKernelGGL((combine1_kernel<ID>), grid, block, 0, s, a);
   } else if (lv == 2) {
-    constexpr int MN = Comb<ID>::MN;
-    dim3 block(64 * MN);
     dim3 grid((unsigned)((a.w + 63) / 64), (unsigned)a.h, (unsigned)ngroups);
-    hipLaunchKernelGGL((combine2_kernel<ID>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((combine2_kernel<ID>), grid, dim3(256), 0, s, a);
   } else {
     return hipErrorInvalidValue;
   }

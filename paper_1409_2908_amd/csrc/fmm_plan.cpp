@@ -47,14 +47,15 @@ int col_nnz(const signed char* X, int rows, int R, int r, int* where, int* coef)
 }
 
 // Levels fused per addition pass (1 or 2).  An explicit request wins, then
-// the FMM_FUSE environment variable; by default two levels are fused only for
-// narrow base cases (R <= 8): fusing wider ones gives each thread hundreds of
-// output streams and measured slower than one level per pass on MI355X.
-int resolve_fuse(int requested, int R) {
+// the FMM_FUSE environment variable; by default two levels are fused (fewer
+// bytes: the level-one intermediates are never written), except for BF16x3
+// plans of wide base cases (R > 8), whose split T operands in k-octets are
+// formed by the register kernel, which measured slower fused than unfused.
+int resolve_fuse(int requested, int R, int dtype) {
   if (requested == 1 || requested == 2) return requested;
   const char* e = std::getenv("FMM_FUSE");
   if (e && (e[0] == '1' || e[0] == '2') && e[1] == 0) return e[0] - '0';
-  return R <= 8 ? 2 : 1;
+  return (dtype == 2 && R > 8) ? 1 : 2;  // dtype 2: FP32 inputs with BF16x3 leaves
 }
 
 // Splits L levels into passes of at most `fuse` levels.  Operand formation
@@ -275,7 +276,7 @@ std::string summarize_plan(PlanSummary& S, const char* alg, int64_t m, int64_t k
     if (m > 0 && n > 0) S.groups.push_back(GemmGroup{m, n, k, 1, 0, 0, 0, 0});
   } else {
     const AlgInfo& A = alg_info(id);
-    S.fuse = resolve_fuse(fuse, A.R);
+    S.fuse = resolve_fuse(fuse, A.R, dtype);
     const int64_t fm = ipow(A.M, L), fk = ipow(A.K, L), fn = ipow(A.N, L);
     const int64_t m0 = m / fm * fm, k0 = k / fk * fk, n0 = n / fn * fn;
     const int64_t ml = m0 / fm, kl = k0 / fk, nl = n0 / fn;
@@ -361,7 +362,7 @@ std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n,
     P.K = A.K;
     P.N = A.N;
     P.R = A.R;
-    P.fuse = resolve_fuse(fuse, A.R);
+    P.fuse = resolve_fuse(fuse, A.R, dtype);
     const int64_t fm = ipow(A.M, P.levels), fk = ipow(A.K, P.levels), fn = ipow(A.N, P.levels);
     P.m0 = m / fm * fm;
     P.k0 = k / fk * fk;
