@@ -154,3 +154,22 @@ def test_split_leaf_operands_bit_exact(F, alg, L, kmul):
             got_h = raw_h.transpose(0, 2, 1).reshape(groups * 8, ln)[:lk]
             got_l = raw_l.transpose(0, 2, 1).reshape(groups * 8, ln)[:lk]
             assert np.array_equal(got_h, _bf16_bits(th)) and np.array_equal(got_l, _bf16_bits(tl)), ("T", leaf)
+
+
+@pytest.mark.parametrize("alg,L", [("fmm_424_26", 2), ("fmm_333_23", 2), ("strassen_222_7", 2)])
+@pytest.mark.parametrize("dtype_name", ["F32_BF16X3", "F32"])
+def test_fp32_fused_levels_bitwise_equal_unfused(F, alg, L, dtype_name, monkeypatch):
+    """With FP32 operands the operand sums and the W-combination are binary64
+    chains rounded once to FP32 (and split once on the BF16x3 path), so two
+    levels per pass -- the LDS kernels for wide base cases and the split-S
+    outputs they write -- give the same bits as one level per pass."""
+    dtype = getattr(F, dtype_name)
+    a = algorithms.get(alg)
+    m, k, n = a.M ** L * 5 + 1, a.K ** L * 7 + 2, a.N ** L * 3 + 1
+    say(f"case fp32 fuse {dtype_name} {alg} L={L} m={m} k={k} n={n}")
+    A, B = fmm_inputs.operands(21, m, k, n, "normal_rowscaled", np.float32)
+    out = {}
+    for fuse in ("1", "2"):
+        monkeypatch.setenv("FMM_FUSE", fuse)
+        out[fuse] = _run(F, alg, L, A, B, dtype)
+    assert np.array_equal(out["1"].view(np.int32), out["2"].view(np.int32))
