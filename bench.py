@@ -262,6 +262,12 @@ def run_serving(args):
     log(f"[serving] Poisson at {rate:.1f} req/s, one-at-a-time classical: {cl}")
     checked = serving.check_alone(kept)
     log(f"[serving] {checked} requests recomputed alone: bitwise equal")
+    cap_graph, _ = serving.run_stream(reqs, zeros, pools, use_graph=True, **common)
+    log(f"[serving] capacity, fast path, one HIP graph per batch: {cap_graph}")
+    fast_graph, kept_g = serving.run_stream(reqs, arr, pools, keep=keep, use_graph=True, **common)
+    log(f"[serving] Poisson at {rate:.1f} req/s, fast path, one HIP graph per batch: {fast_graph}")
+    checked_g = serving.check_alone(kept_g)
+    log(f"[serving] {checked_g} graph-served requests recomputed alone: bitwise equal")
     out = {
         "metric": "serving throughput (requests/s, effective TFLOP/s) and p50/p99 latency",
         "value": round(fast["req_per_s"], 3), "unit": "requests/s", "n_gpus": 1,
@@ -272,7 +278,8 @@ def run_serving(args):
         "offered_req_per_s": round(rate, 3),
         "fast": fast, "classical_one_at_a_time": cl,
         "capacity_fast": cap_fast, "capacity_classical": cap_cl,
-        "alone_vs_mix_checked": checked,
+        "fast_graph": fast_graph, "capacity_fast_graph": cap_graph,
+        "alone_vs_mix_checked": checked, "alone_vs_mix_checked_graph": checked_g,
     }
     print(json.dumps(out), flush=True)
 

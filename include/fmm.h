@@ -259,7 +259,8 @@ fmm_status fmm_tune_clear(void);
  * arrival order while the device arena (workspaces and descriptor tables)
  * has room and fewer than max_inflight batches are pending; each admitted
  * batch of up to max_batch requests is enqueued as one fmm_multiply_batched
- * on the server's stream and followed by one completion event.  Planning of
+ * (or, with use_graph, as one HIP graph recorded from it) on the server's
+ * stream and followed by one completion event.  Planning of
  * the next batch on the host overlaps the running batch on the device.  The
  * caller owns A, B and C of every request and keeps them alive until the
  * request completes.  Single-threaded: call every fmm_server_* function of
@@ -271,6 +272,9 @@ typedef struct {
     int max_batch;       /* requests per batch, 1..64 (leaves of up to 8 share a launch) */
     int max_inflight;    /* batches enqueued and not finished, >= 1 */
     int fuse_levels;     /* as fmm_plan_options_t */
+    int use_graph;       /* non-zero: each batch's launches are recorded into a HIP graph
+                            (kernel nodes only), instantiated once and launched as one
+                            graph; the executable graph is freed when the batch completes */
 } fmm_server_options_t;
 
 typedef struct {

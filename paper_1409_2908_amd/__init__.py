@@ -64,7 +64,7 @@ class _Candidate(ctypes.Structure):
 
 class _ServerOptions(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int),
-                ("max_inflight", ctypes.c_int), ("fuse_levels", ctypes.c_int)]
+                ("max_inflight", ctypes.c_int), ("fuse_levels", ctypes.c_int), ("use_graph", ctypes.c_int)]
 
 
 class _Request(ctypes.Structure):
@@ -341,9 +341,10 @@ class Server:
     """Continuous-batching request server (fmm_server_*).  Keeps the operand
     tensors of every request alive until its completion has been returned."""
 
-    def __init__(self, arena_bytes, max_batch=8, max_inflight=2, fuse_levels=0, stream=None):
+    def __init__(self, arena_bytes, max_batch=8, max_inflight=2, fuse_levels=0, stream=None, use_graph=False):
         self._s = ctypes.c_void_p()
-        opts = _ServerOptions(int(arena_bytes), int(max_batch), int(max_inflight), int(fuse_levels))
+        opts = _ServerOptions(int(arena_bytes), int(max_batch), int(max_inflight), int(fuse_levels),
+                              1 if use_graph else 0)
         sp = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
         _check(_lib.fmm_server_create(ctypes.byref(self._s), ctypes.byref(opts), sp))
         self._live = {}

@@ -89,6 +89,7 @@ struct Batch {
   hipEvent_t ev;
   double launch_ms;
   std::vector<Admitted> reqs;
+  hipGraphExec_t exec = nullptr;  // the batch's graph (use_graph), freed when it completes
 };
 
 }  // namespace
@@ -98,6 +99,7 @@ struct fmm_server_s {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t cap_stream = nullptr;  // records batch graphs (use_graph); never runs work
   char* arena_mem = nullptr;
   Arena arena;
   std::deque<Queued> queue;
@@ -135,6 +137,10 @@ void complete(fmm_server_s& S, int64_t id, void* user, fmm_status st, double sub
 }
 
 void finish_batch(fmm_server_s& S, Batch& b, fmm_status st) {
+  if (b.exec) {
+    (void)hipGraphExecDestroy(b.exec);
+    b.exec = nullptr;
+  }
   for (Admitted& a : b.reqs) {
     S.arena.release(a.off, a.bytes);
     (void)fmm_plan_destroy(a.plan);
@@ -158,6 +164,41 @@ fmm_status retire(fmm_server_s& S, bool block) {
     finish_batch(S, b, FMM_OK);
     S.inflight.pop_front();
   }
+  return FMM_OK;
+}
+
+// use_graph: records the batch's launches (kernels only: the descriptor
+// tables were uploaded when the plans were bound) on the capture stream,
+// instantiates the graph and launches it on the server's stream.  Every
+// batch holds other requests, so each is instantiated once; the executable
+// graph lives until the batch's completion event has been seen.
+fmm_status launch_graph(fmm_server_s& S, Batch& b, std::vector<fmm_plan_t>& plans, std::vector<const void*>& A,
+                        std::vector<int64_t>& lda, std::vector<const void*>& B, std::vector<int64_t>& ldb,
+                        std::vector<void*>& C, std::vector<int64_t>& ldc) {
+  hipError_t e;
+  if (!S.cap_stream) {
+    e = hipStreamCreateWithFlags(&S.cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(FMM_EHIP, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
+  }
+  e = hipStreamBeginCapture(S.cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return fail(FMM_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  const fmm_status st = fmm_multiply_batched(plans.data(), A.data(), lda.data(), B.data(), ldb.data(), C.data(),
+                                             ldc.data(), (int)plans.size(), S.cap_stream);
+  const std::string err = st != FMM_OK ? std::string(fmm_last_error()) : std::string();
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(S.cap_stream, &g);
+  if (st != FMM_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return st != FMM_OK ? fail(st, err) : fail(FMM_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  }
+  e = hipGraphInstantiate(&b.exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b.exec = nullptr;
+    return fail(FMM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  e = hipGraphLaunch(b.exec, S.stream);
+  if (e != hipSuccess) return fail(FMM_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
   return FMM_OK;
 }
 
@@ -229,8 +270,10 @@ fmm_status admit(fmm_server_s& S) {
     b.ev = S.spare_events.back();
     S.spare_events.pop_back();
     b.launch_ms = S.now_ms();
-    fmm_status st = fmm_multiply_batched(plans.data(), A.data(), lda.data(), B.data(), ldb.data(), C.data(),
-                                         ldc.data(), (int)nb, S.stream);
+    fmm_status st = S.opt.use_graph
+                        ? launch_graph(S, b, plans, A, lda, B, ldb, C, ldc)
+                        : fmm_multiply_batched(plans.data(), A.data(), lda.data(), B.data(), ldb.data(), C.data(),
+                                               ldc.data(), (int)nb, S.stream);
     hipError_t e = hipEventRecord(b.ev, S.stream);
     if (st != FMM_OK || e != hipSuccess) {
       // nothing of the batch may still read the arena when its ranges are reused
@@ -346,12 +389,14 @@ fmm_status fmm_server_destroy(fmm_server_t s) {
   for (Batch& b : s->inflight) {
     for (Admitted& a : b.reqs) (void)fmm_plan_destroy(a.plan);
     (void)hipEventDestroy(b.ev);
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
   }
   for (Queued& q : s->queue)
     if (q.plan) (void)fmm_plan_destroy(q.plan);
   for (hipEvent_t ev : s->spare_events) (void)hipEventDestroy(ev);
   if (s->arena_mem) (void)hipFree(s->arena_mem);
   if (s->own_stream) (void)hipStreamDestroy(s->stream);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   if (prev != s->device && prev >= 0) (void)hipSetDevice(prev);
   delete s;
   return FMM_OK;

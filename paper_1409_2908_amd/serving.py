@@ -69,14 +69,15 @@ def percentile(x, q):
 
 
 def run_stream(requests, arrivals_ms, pools, arena_bytes, max_batch=8, max_inflight=2, alg=None,
-               levels=-1, keep=None, max_outstanding=64):
+               levels=-1, keep=None, max_outstanding=64, use_graph=False):
     """Replay the stream in real time through a server.  `alg`/`levels` apply
     to every request (None / -1: the library's per-shape choice).  At most
     `max_outstanding` requests are submitted and unfinished at once (their
     outputs are allocated); later arrivals wait on the host, and that wait
     counts in their latency.  `keep` is a set of request indices whose A, B,
-    C, dtype and completion are returned for checking.  Returns a dict of
-    metrics and the kept results."""
+    C, dtype and completion are returned for checking.  use_graph: every batch
+    runs as one recorded HIP graph.  Returns a dict of metrics and the kept
+    results."""
     import torch
     n = len(requests)
     lat, flops = np.zeros(n), 0.0
@@ -84,7 +85,7 @@ def run_stream(requests, arrivals_ms, pools, arena_bytes, max_batch=8, max_infli
     meta = {}
     batches = []
     algs = {}
-    srv = Server(arena_bytes, max_batch=max_batch, max_inflight=max_inflight)
+    srv = Server(arena_bytes, max_batch=max_batch, max_inflight=max_inflight, use_graph=use_graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     i = done = 0

@@ -43,3 +43,22 @@ def test_poisson_stream_alone_vs_mix_and_oracle():
             emu = bf16x3.gemm(A, B) if a is None else bf16x3.fmm(a, c["levels"], A, B)
             assert relf(C, emu) <= 2e-6 * 2 ** max(c["levels"], 1), (idx, c)
     torch.cuda.synchronize()
+
+
+def test_graph_served_batches_equal_eager():
+    """With one recorded HIP graph per batch, every request's result is bit
+    for bit the same plan run alone (the graph holds the same kernels with
+    the same arguments)."""
+    import torch
+    from paper_1409_2908_amd import serving
+    n_req = 120
+    reqs = serving.make_requests(31, n_req, lo=64, hi=1024)
+    pools = serving.Pools(2048, seed=7)
+    arr = np.zeros(n_req)
+    say(f"case graph-served stream {n_req} requests")
+    stats, kept = serving.run_stream(reqs, arr, pools, arena_bytes=1 << 30, max_batch=8, max_inflight=2,
+                                     keep=set(range(n_req)), max_outstanding=32, use_graph=True)
+    say(f"  {stats}")
+    assert stats["requests"] == n_req and stats["mean_batch"] > 1
+    assert serving.check_alone(kept) == n_req
+    torch.cuda.synchronize()
