@@ -99,6 +99,10 @@ typedef struct {
                           stage timing is on. */
     int defer_device_memory; /* non-zero: allocate nothing on the device; the caller binds
                           fmm_plan_device_bytes(p) bytes with fmm_plan_bind before running */
+    int leaf_tile;     /* output tile edge of the FP64 / FP32 leaf GEMM: 128 or 64; 0 (default):
+                          chosen per launch, 64 when the launch has fewer 128 x 128 tiles than
+                          the device has compute units.  BF16x3 leaves always use 128.  Other
+                          values: FMM_EINVAL.  Batched launches always choose per launch. */
 } fmm_plan_options_t;
 
 /* Plan C = A*B for an m x k by k x n product with `levels` recursive steps of

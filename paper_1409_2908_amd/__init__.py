@@ -53,7 +53,8 @@ class _Info(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("fuse_levels", ctypes.c_int), ("host_only", ctypes.c_int),
-                ("use_graph", ctypes.c_int), ("defer_device_memory", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("defer_device_memory", ctypes.c_int),
+                ("leaf_tile", ctypes.c_int)]
 
 
 class _Candidate(ctypes.Structure):
@@ -179,11 +180,11 @@ class Plan:
     (``fmm_plan_host``) can be inspected but not run."""
 
     def __init__(self, alg, m, k, n, levels, dtype=F64, host_only=False, fuse_levels=0,
-                 use_graph=False, defer_device_memory=False):
+                 use_graph=False, defer_device_memory=False, leaf_tile=0):
         self._p = ctypes.c_void_p()
         self.dtype = _dtype_code(dtype)
         opts = _Options(int(fuse_levels), 1 if host_only else 0, 1 if use_graph else 0,
-                        1 if defer_device_memory else 0)
+                        1 if defer_device_memory else 0, int(leaf_tile))
         _check(_lib.fmm_plan_ex(ctypes.byref(self._p), alg.encode(), m, k, n, levels, self.dtype,
                                 ctypes.byref(opts)))
         self.m, self.k, self.n = m, k, n

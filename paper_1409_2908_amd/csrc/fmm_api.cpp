@@ -173,6 +173,7 @@ hipError_t run_leaf(const fmm::Plan& P, const fmm::Bases& b, hipStream_t s) {
   fmm::GemmArgs a;
   std::memset(&a, 0, sizeof(a));
   append_leaf(a, P, b, 0);
+  a.tile = P.leaf_tile;
   return fmm::launch_gemm(a, P.dtype, num_cus(P.device), s);
 }
 
@@ -274,9 +275,11 @@ fmm_status capture_graph(fmm::Plan& P, const fmm::Bases& b) {
 }
 
 fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
-                       int dtype, int fuse, bool device, bool defer = false, bool graph = false) {
+                       int dtype, int fuse, bool device, bool defer = false, bool graph = false,
+                       int leaf_tile = 0) {
   if (!out) return fail(FMM_EINVAL, "out is NULL");
   *out = nullptr;
+  if (leaf_tile != 0 && leaf_tile != 64 && leaf_tile != 128) return fail(FMM_EINVAL, "leaf_tile must be 0, 64 or 128");
   fmm_status st = check_tables_once();
   if (st != FMM_OK) return st;
   if (dtype == FMM_F32_BF16X3 && !fmm::kHaveBf16x3)
@@ -306,6 +309,7 @@ fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
     return fail((fmm_status)code, err);
   }
   fmm::Plan& P = h->P;
+  P.leaf_tile = leaf_tile;
   if (device) {
     if (const char* bud = std::getenv("FMM_HBM_BUDGET")) {
       const double budget = std::atof(bud);
@@ -381,7 +385,8 @@ fmm_status fmm_plan_ex(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
   const bool host_only = opts && opts->host_only;
   const bool defer = opts && opts->defer_device_memory;
   const bool graph = opts && opts->use_graph;
-  return plan_common(out, alg, m, k, n, levels, dtype, fuse, !host_only, defer, graph);
+  const int tile = opts ? opts->leaf_tile : 0;
+  return plan_common(out, alg, m, k, n, levels, dtype, fuse, !host_only, defer, graph, tile);
 }
 
 size_t fmm_plan_device_bytes(fmm_plan_t p) {

@@ -110,6 +110,8 @@ struct GemmArgs {
   GemmProb single;
   int ngroups;
   int elt;
+  int tile;  // output tile edge of the FP64 / FP32 kernel: 64, 128, or 0 (chosen at launch)
+  int pad_;
   int64_t total_tiles;
   GemmGroup groups[kMaxGemmGroups];
 };
@@ -176,6 +178,7 @@ struct Plan {
   int64_t timed = 0;            // timed multiplies since timing was enabled
   bool external = false;        // device memory bound by the caller (not owned)
   bool use_graph = false;       // replay the stages as a captured HIP graph
+  int leaf_tile = 0;            // FP64 / FP32 leaf tile edge: 64, 128, or 0 (chosen per launch)
   void* graph_exec = nullptr;   // hipGraphExec_t of the last capture
   void* cap_stream = nullptr;   // private stream the capture is recorded on
   Bases graph_key{};            // operand bases the captured graph was made for
@@ -240,5 +243,14 @@ bool choose(int64_t m, int64_t k, int64_t n, int dtype, const char* alg, int lev
             Candidate* pick, std::string* why);
 
 constexpr int64_t kTileM = 128, kTileN = 128;
+
+// Whether an FP64 / FP32 leaf launch of `tiles128` tiles of kTileM x kTileN
+// on `cus` compute units runs 64 x 64 tiles instead: when the large tiles
+// would leave compute units idle -- fewer tiles than compute units, or at
+// most four waves of two tiles per CU whose last wave is at most half full.
+inline bool use_small_tiles(int64_t tiles128, int64_t cus) {
+  const int64_t rem = tiles128 % (2 * cus);
+  return tiles128 < cus || (tiles128 < 4 * cus && rem > 0 && rem <= cus);
+}
 
 }  // namespace fmm

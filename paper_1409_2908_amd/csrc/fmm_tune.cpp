@@ -39,6 +39,10 @@ constexpr double kAddBw = 4.8e12;           // byte/s, formation / combination p
 constexpr double kLaunch = 6e-6;       // s per kernel launch on a busy stream
 constexpr double kFix = 32;            // per-tile fixed cost, in units of k
 constexpr int kSlots = 512;            // resident leaf workgroups (2 per compute unit)
+constexpr int kCUs = kSlots / 2;
+constexpr int kSlotsSmall = 4 * kCUs;  // resident 64 x 64 leaf workgroups (4 per compute unit)
+// full-occupancy rate of the 64 x 64 tile relative to the 128 x 128 one
+constexpr double kSmallF64 = 0.93, kSmallF32 = 0.74;
 constexpr int64_t kMaxLeaves = 60000;  // candidates with more leaves are not offered
 
 // Rate of group g of a plan: on the BF16x3 path the leaf group (the first
@@ -62,11 +66,27 @@ void predict(const PlanSummary& P, int dtype, Candidate& c) {
     tiles += t;
     wmax = std::max(wmax, w);
   }
+  // Tiles of one launch share the compute units: with fewer tiles than
+  // resident slots each compute unit holds ceil(tiles / CUs) of them and
+  // splits its rate among those.
+  auto waves_time = [](double u, double w, double ntiles, int per_cu, double tile_edge, double r) {
+    const double resident = std::min<double>(per_cu, std::max(1.0, std::ceil(ntiles / kCUs)));
+    const double slots = kCUs * resident;
+    return std::ceil(u / (slots * w)) * w * 2.0 * tile_edge * tile_edge / (r / slots);
+  };
   double leaf_s = 0;
-  if (tiles > 0) {
-    const double waves = std::ceil(units / (kSlots * wmax));
-    const double per_unit = 2.0 * kTileM * kTileN / (ref / kSlots);
-    leaf_s = waves * wmax * per_unit;
+  if (tiles > 0 && dtype != 2 && use_small_tiles((int64_t)tiles, kCUs)) {
+    // the launch runs 64 x 64 tiles (FP64 / FP32 only; every group at the
+    // same rate on these paths)
+    double units64 = 0, tiles64 = 0;
+    for (const GemmGroup& g : P.groups) {
+      const double t = (double)((g.m + 63) / 64) * ((g.n + 63) / 64) * g.count;
+      units64 += t * ((double)g.k + kFix);
+      tiles64 += t;
+    }
+    leaf_s = waves_time(units64, wmax, tiles64, kSlotsSmall / kCUs, 64, ref * (dtype == 0 ? kSmallF64 : kSmallF32));
+  } else if (tiles > 0) {
+    leaf_s = waves_time(units, wmax, tiles, kSlots / kCUs, (double)kTileM, ref);
   }
   const double add_s = P.add_bytes / kAddBw;
   const double launches = 1.0 + P.form_passes + P.comb_passes;

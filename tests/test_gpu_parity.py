@@ -279,3 +279,30 @@ def test_bench_configuration_sampled_rows(F):
     err = relf(got, ref)
     say(f"  sampled {len(rows)} rows relF={err:.3e}")
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("dtype_name", ["F64", "F32"])
+@pytest.mark.parametrize("alg,L,shape", [("classical", 0, (300, 211, 515)), ("classical", 0, (1, 1000, 129)),
+                                         ("strassen_222_7", 1, (517, 260, 383)),
+                                         ("fmm_424_26", 1, (1030, 777, 1029))])
+def test_leaf_tile_shapes_agree(F, dtype_name, alg, L, shape):
+    """The 64 x 64 and 128 x 128 leaf tiles accumulate every output element
+    over the same K steps in the same order, so they agree bit for bit; both
+    match the oracle (the FP64 and FP32 tolerances above)."""
+    dtype = getattr(F, dtype_name)
+    np_dt = np.float64 if dtype_name == "F64" else np.float32
+    m, k, n = shape
+    say(f"case leaf tiles {dtype_name} {alg} L={L} {m}x{k}x{n}")
+    A, B = fmm_inputs.operands(17, m, k, n, "uniform", np_dt)
+    out = {}
+    for tile in (64, 128, 0):
+        with F.Plan(alg, m, k, n, L, dtype, leaf_tile=tile) as p:
+            out[tile] = to_host(p.multiply(to_dev(A), to_dev(B)))
+    ref = classical.gemm(A, B)
+    tol = 1e-12 if dtype_name == "F64" else 2e-6 * 2 ** L
+    for tile in (64, 128):
+        assert relf(out[tile], ref) <= tol, tile
+    iv = np.int64 if dtype_name == "F64" else np.int32
+    assert np.array_equal(out[64].view(iv), out[128].view(iv))
+    assert np.array_equal(out[0].view(iv), out[64].view(iv))
+

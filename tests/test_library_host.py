@@ -55,6 +55,13 @@ def test_unknown_algorithm_and_bad_args():
     assert e.value.code == 1
     with pytest.raises(F.FmmError):
         F.Plan("strassen_222_7", 8, 8, 8, 1, dtype=7, host_only=True)
+    # leaf tile edge: 0 (per launch), 64 or 128 only
+    for tile in (0, 64, 128):
+        F.Plan("strassen_222_7", 8, 8, 8, 1, host_only=True, leaf_tile=tile).close()
+    for tile in (-1, 32, 96, 256):
+        with pytest.raises(F.FmmError) as e:
+            F.Plan("strassen_222_7", 8, 8, 8, 1, host_only=True, leaf_tile=tile)
+        assert e.value.code == 1
 
 
 def _ipow(b, e):
