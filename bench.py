@@ -82,7 +82,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on exactly one GPU; the fast-multiplication hot path is "
+        print("bench.py: runs on exactly one GPU; the fast-multiplication hot path is "
               "measured per GPU (--gpus 1).  Multi-GPU sharding is design-only.", file=sys.stderr)
         sys.exit(2)
 
@@ -188,10 +188,14 @@ def main():
 
     leaf_ms = stage_ms[F.STAGE_LEAF]
     leaf_tflops = info["leaf_flops"] / (leaf_ms * 1e-3) / 1e12
+    # the leaf launch's tile edge (the library's per-launch rule for FP64 / FP32)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    t128, rem = info["gemm_tiles"], info["gemm_tiles"] % (2 * cus)
+    tile = 64 if (t128 < cus or (t128 < 4 * cus and 0 < rem <= cus)) else 128
     if dt == F.F64:
-        kernel, peak, tag = "gemm_kernel<double>", FP64_PEAK_TFLOPS, "gemm_f64"
+        kernel, peak, tag = f"gemm_kernel<double, {tile}, {tile}>", FP64_PEAK_TFLOPS, f"gemm_f64_t{tile}"
     elif dt == F.F32:
-        kernel, peak, tag = "gemm_kernel<float>", FP32_PEAK_TFLOPS, "gemm_f32"
+        kernel, peak, tag = f"gemm_kernel<float, {tile}, {tile}>", FP32_PEAK_TFLOPS, f"gemm_f32_t{tile}"
     else:
         # three bf16 products per FP32 product, priced at the bf16 matrix peak
         kernel, peak, tag = "gemm_bf16x3_kernel", BF16_PEAK_TFLOPS, "gemm_bf16x3"
@@ -340,9 +344,9 @@ def run_sweep(args):
             cms = timed(lambda: F.gemm(A, B, C))
             t = autotune.tune(m, k, n, F.F64, top=6)
             emit({"shape": [m, k, n], "classical_ms": cms, "classical_tflops": fl / cms / 1e9,
-                  "tuned": {x: t[x] for x in ("alg", "levels", "fuse_levels", "ms", "tflops")},
+                  "tuned": {x: t[x] for x in ("alg", "levels", "fuse_levels", "leaf_tile", "ms", "tflops")},
                   "speedup": cms / t["ms"], "model_top": F.rank_candidates(m, k, n, F.F64)[0],
-                  "candidates": [{x: c.get(x) for x in ("alg", "levels", "fuse_levels", "model_ms", "ms")}
+                  "candidates": [{x: c.get(x) for x in ("alg", "levels", "fuse_levels", "leaf_tile", "model_ms", "ms")}
                                  for c in t["candidates"]]})
             del A, B, C
             torch.cuda.empty_cache()

@@ -41,7 +41,7 @@ typedef enum {
                               overlapping C, depth that leaves a leaf dimension < 1 */
     FMM_ENOMEM = 2,        /* workspace beyond the budget, or device allocation failed */
     FMM_EHIP = 3,          /* a HIP runtime or launch failure (message has the HIP error) */
-    FMM_EUNSUPPORTED = 4,  /* dtype / option not supported by this build */
+    FMM_EUNSUPPORTED = 4,  /* dtype / option not compiled into this library */
     FMM_EALG = 5           /* unknown algorithm, or a table that fails the Brent check */
 } fmm_status;
 
@@ -85,6 +85,7 @@ typedef struct {
     int fuse_levels;             /* recursion levels formed / combined per addition pass */
     char alg[32];                /* base case planned ("classical" for a plain GEMM); for
                                     "auto" the cost model's choice */
+    int leaf_tile;               /* leaf tile edge asked for (64 / 128), 0: chosen per launch */
 } fmm_plan_info_t;
 
 /* Options of fmm_plan_ex.  Zero-initialise, then set what you need. */
@@ -236,6 +237,7 @@ typedef struct {
     char alg[32];        /* "classical" or a base-case name */
     int levels;
     int fuse_levels;
+    int leaf_tile;       /* leaf tile edge of a recorded choice (64 / 128); 0: chosen per launch */
     double model_ms;     /* predicted time */
     double leaf_ms, add_ms;
     size_t workspace_bytes;
@@ -252,10 +254,11 @@ fmm_status fmm_rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const
  * process-wide table: later fmm_plan calls with alg "auto" and levels -1 for
  * that shape, and server requests of that shape with alg NULL/"auto" and
  * levels -1, plan it (when its workspace fits the budget) instead of the
- * model's pick.  The choice is validated by planning it on the host.
+ * model's pick, with its fuse_levels and leaf_tile (0, 64 or 128, as in
+ * fmm_plan_options_t).  The choice is validated by planning it on the host.
  * fmm_tune_clear empties the table.  Thread-safe. */
 fmm_status fmm_tune_record(int64_t m, int64_t k, int64_t n, int dtype, const char *alg, int levels,
-                           int fuse_levels);
+                           int fuse_levels, int leaf_tile);
 fmm_status fmm_tune_clear(void);
 
 /* ---- Serving runtime: continuous batching ---------------------------------

@@ -14,12 +14,12 @@ import ctypes
 import json
 import os
 
-from . import F64, FmmError, Plan, _check, _dtype_code, _lib, rank_candidates
+from . import F32_BF16X3, F64, FmmError, Plan, _check, _dtype_code, _lib, rank_candidates
 
 __all__ = ["tune", "load_cache", "record", "clear"]
 
 _lib.fmm_tune_record.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
-                                 ctypes.c_char_p, ctypes.c_int, ctypes.c_int]
+                                 ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
 _lib.fmm_tune_record.restype = ctypes.c_int
 _lib.fmm_tune_clear.argtypes = []
 _lib.fmm_tune_clear.restype = ctypes.c_int
@@ -29,9 +29,10 @@ def _key(m, k, n, dtype):
     return f"{m}x{k}x{n}:{dtype}"
 
 
-def record(m, k, n, dtype, alg, levels, fuse_levels=0):
+def record(m, k, n, dtype, alg, levels, fuse_levels=0, leaf_tile=0):
     """Register a choice for the exact shape with the library."""
-    _check(_lib.fmm_tune_record(m, k, n, _dtype_code(dtype), alg.encode(), int(levels), int(fuse_levels)))
+    _check(_lib.fmm_tune_record(m, k, n, _dtype_code(dtype), alg.encode(), int(levels), int(fuse_levels),
+                                int(leaf_tile)))
 
 
 def clear():
@@ -46,7 +47,8 @@ def load_cache(path):
         data = json.load(f)
     for key, e in data.items():
         m, k, n = (int(x) for x in key.split(":")[0].split("x"))
-        record(m, k, n, int(key.split(":")[1]), e["alg"], e["levels"], e.get("fuse_levels", 0))
+        record(m, k, n, int(key.split(":")[1]), e["alg"], e["levels"], e.get("fuse_levels", 0),
+               e.get("leaf_tile", 0))
     return len(data)
 
 
@@ -67,9 +69,11 @@ def _time_plan(p, A, B, C, reps, warmup):
 
 def tune(m, k, n, dtype=F64, top=4, reps=3, warmup=1, cache=None, budget_bytes=0, seed=0):
     """Time the model's `top` candidates (and the classical product) for the
-    shape on the current device; record and return the fastest as a dict
-    {alg, levels, fuse_levels, ms, tflops, candidates: [...]}, where each
-    candidate carries its model prediction and measured ms."""
+    shape on the current device, each with one and two levels per addition
+    pass where both exist and, on the FP64 / FP32 paths, with 64 x 64 and
+    128 x 128 leaf tiles; record and return the fastest as a dict
+    {alg, levels, fuse_levels, leaf_tile, ms, tflops, candidates: [...]},
+    where each candidate carries its model prediction and measured ms."""
     import torch
     dtype = _dtype_code(dtype)
     elt = torch.float64 if dtype == F64 else torch.float32
@@ -82,23 +86,26 @@ def tune(m, k, n, dtype=F64, top=4, reps=3, warmup=1, cache=None, budget_bytes=0
     B = torch.rand((k, n), dtype=elt, device="cuda", generator=g) * 2 - 1
     C = torch.empty((m, n), dtype=elt, device="cuda")
     results = []
+    tiles = [0] if dtype == F32_BF16X3 else [64, 128]
     for c in trial:
         fuses = [0] if c["levels"] == 0 else ([1, 2] if c["levels"] >= 2 else [1])
         for fz in fuses:
-            try:
-                with Plan(c["alg"], m, k, n, c["levels"], dtype, fuse_levels=fz) as p:
-                    ms = _time_plan(p, A, B, C, reps, warmup)
-                    fz_used = p.info["fuse_levels"]
-            except FmmError as e:  # e.g. workspace beyond memory: not a candidate here
-                results.append(dict(c, fuse_levels=fz, ms=None, error=str(e)))
-                continue
-            results.append(dict(c, fuse_levels=fz_used, ms=ms))
+            for tile in tiles:
+                try:
+                    with Plan(c["alg"], m, k, n, c["levels"], dtype, fuse_levels=fz, leaf_tile=tile) as p:
+                        ms = _time_plan(p, A, B, C, reps, warmup)
+                        fz_used = p.info["fuse_levels"]
+                except FmmError as e:  # e.g. workspace beyond memory: not a candidate here
+                    results.append(dict(c, fuse_levels=fz, leaf_tile=tile, ms=None, error=str(e)))
+                    continue
+                results.append(dict(c, fuse_levels=fz_used, leaf_tile=tile, ms=ms))
     ok = [r for r in results if r["ms"] is not None]
     if not ok:
         raise FmmError(2, "no candidate could run")
     best = min(ok, key=lambda r: r["ms"])
-    record(m, k, n, dtype, best["alg"], best["levels"], best["fuse_levels"])
+    record(m, k, n, dtype, best["alg"], best["levels"], best["fuse_levels"], best["leaf_tile"])
     out = {"alg": best["alg"], "levels": best["levels"], "fuse_levels": best["fuse_levels"],
+           "leaf_tile": best["leaf_tile"],
            "ms": best["ms"], "tflops": 2.0 * m * k * n / (best["ms"] * 1e-3) / 1e12,
            "candidates": results}
     if cache:
@@ -106,7 +113,7 @@ def tune(m, k, n, dtype=F64, top=4, reps=3, warmup=1, cache=None, budget_bytes=0
         if os.path.exists(cache):
             with open(cache) as f:
                 data = json.load(f)
-        data[_key(m, k, n, dtype)] = {x: out[x] for x in ("alg", "levels", "fuse_levels", "ms")}
+        data[_key(m, k, n, dtype)] = {x: out[x] for x in ("alg", "levels", "fuse_levels", "leaf_tile", "ms")}
         tmp = cache + ".tmp"
         with open(tmp, "w") as f:
             json.dump(data, f, indent=1, sort_keys=True)

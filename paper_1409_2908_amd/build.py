@@ -35,7 +35,7 @@ def _compile(src, verbose):
 
 def build(verbose=False):
     # load the generator by path: importing the package would load the
-    # (possibly stale) library this build is about to replace
+    # (possibly stale) library this call is about to replace
     import importlib.util
     spec = importlib.util.spec_from_file_location(
         "fmm_gen_tables", os.path.join(HERE, "algorithms", "gen_tables.py"))

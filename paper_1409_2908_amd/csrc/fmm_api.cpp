@@ -283,7 +283,7 @@ fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
   fmm_status st = check_tables_once();
   if (st != FMM_OK) return st;
   if (dtype == FMM_F32_BF16X3 && !fmm::kHaveBf16x3)
-    return fail(FMM_EUNSUPPORTED, "BF16x3 leaves are not available in this build");
+    return fail(FMM_EUNSUPPORTED, "BF16x3 leaves are not compiled into this library");
   // "auto" (any base case) or levels -1 (best depth of `alg`): the cost model's choice
   std::string chosen;
   if ((alg && !std::strcmp(alg, "auto")) || levels < 0) {
@@ -299,6 +299,7 @@ fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
     alg = chosen.c_str();
     levels = pick.levels;
     if (!fuse) fuse = pick.fuse;
+    if (!leaf_tile) leaf_tile = pick.tile;
   }
   fmm_plan_s* h = new (std::nothrow) fmm_plan_s();
   if (!h) return fail(FMM_ENOMEM, "host allocation failed");
@@ -615,6 +616,7 @@ fmm_status fmm_plan_info(fmm_plan_t p, fmm_plan_info_t* info) {
   info->fuse_levels = P.levels > 0 ? P.fuse : 0;
   info->gemm_min_bytes = P.gemm_min_bytes;
   std::snprintf(info->alg, sizeof(info->alg), "%s", P.alg_id < 0 ? "classical" : fmm::alg_info(P.alg_id).name);
+  info->leaf_tile = P.leaf_tile;
   return FMM_OK;
 }
 
@@ -644,7 +646,7 @@ fmm_status fmm_gemm(int dtype, int64_t m, int64_t k, int64_t n, const void* A, i
   if (m < 0 || k < 0 || n < 0) return fail(FMM_EINVAL, "sizes must be non-negative");
   if (dtype < 0 || dtype > 2) return fail(FMM_EINVAL, "unknown dtype");
   if (dtype == FMM_F32_BF16X3 && !fmm::kHaveBf16x3)
-    return fail(FMM_EUNSUPPORTED, "BF16x3 leaves are not available in this build");
+    return fail(FMM_EUNSUPPORTED, "BF16x3 leaves are not compiled into this library");
   fmm::Plan P;
   P.m = m;
   P.k = k;
@@ -725,6 +727,7 @@ fmm_status fmm_rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const
     std::snprintf(out[i].alg, sizeof(out[i].alg), "%s", cands[i].alg);
     out[i].levels = cands[i].levels;
     out[i].fuse_levels = cands[i].fuse;
+    out[i].leaf_tile = cands[i].tile;
     out[i].model_ms = cands[i].model_ms;
     out[i].leaf_ms = cands[i].leaf_ms;
     out[i].add_ms = cands[i].add_ms;
@@ -735,12 +738,13 @@ fmm_status fmm_rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const
 }
 
 fmm_status fmm_tune_record(int64_t m, int64_t k, int64_t n, int dtype, const char* alg, int levels,
-                           int fuse_levels) {
+                           int fuse_levels, int leaf_tile) {
   if (m < 0 || k < 0 || n < 0) return fail(FMM_EINVAL, "sizes must be non-negative");
   if (dtype < 0 || dtype > 2) return fail(FMM_EINVAL, "unknown dtype");
   if (!alg) return fail(FMM_EINVAL, "alg is NULL");
   if (fmm::find_algorithm(alg) == -2) return fail(FMM_EALG, std::string("unknown algorithm '") + alg + "'");
   if (levels < 0 || fuse_levels < 0 || fuse_levels > 2) return fail(FMM_EINVAL, "bad levels or fuse_levels");
+  if (leaf_tile != 0 && leaf_tile != 64 && leaf_tile != 128) return fail(FMM_EINVAL, "leaf_tile must be 0, 64 or 128");
   fmm::Plan P;
   int code = 0;
   std::string err = fmm::make_plan(P, alg, m, k, n, levels, dtype, fuse_levels, &code);
@@ -749,6 +753,7 @@ fmm_status fmm_tune_record(int64_t m, int64_t k, int64_t n, int dtype, const cha
   std::snprintf(c.alg, sizeof(c.alg), "%s", alg);
   c.levels = levels;
   c.fuse = fuse_levels;
+  c.tile = leaf_tile;
   fmm::record_tuned(m, k, n, dtype, c);
   return FMM_OK;
 }

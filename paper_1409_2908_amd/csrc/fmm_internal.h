@@ -215,6 +215,7 @@ struct Candidate {
   char alg[32];
   int levels = 0;
   int fuse = 0;
+  int tile = 0;  // leaf tile edge of a recorded choice; 0: chosen per launch
   double model_ms = 0, leaf_ms = 0, add_ms = 0;
   size_t ws_bytes = 0;
 };

@@ -98,10 +98,13 @@ def test_recorded_choice_overrides_the_model(tmp_path):
     model = F.Plan("auto", *shape, -1, host_only=True)
     other = ("fmm_423_20", 1) if model.alg != "fmm_423_20" else ("strassen_222_7", 1)
     try:
-        autotune.record(*shape, F.F64, other[0], other[1], 1)
+        autotune.record(*shape, F.F64, other[0], other[1], 1, 64)
         p = F.Plan("auto", *shape, -1, host_only=True)
         assert (p.alg, p.levels) == other
         assert p.info["fuse_levels"] == 1
+        assert p.info["leaf_tile"] == 64
+        with pytest.raises(F.FmmError):
+            autotune.record(*shape, F.F64, other[0], other[1], 1, 96)
         # only the exact shape and dtype, and only for "auto" at levels -1
         top32 = F.rank_candidates(*shape, F.F32)[0]
         p32 = F.Plan("auto", *shape, -1, dtype=F.F32, host_only=True)
