@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <type_traits>
 
 #include "fmm_gemm_common.h"
 #include "fmm_launch.h"
@@ -366,10 +367,188 @@ __device__ __forceinline__ void bf16x3_tile(Bf16x3Smem& sm, const float* A, cons
       }
 }
 
-__global__ void __launch_bounds__(XNT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+// 64 x 64 tiles (launches whose 128 x 128 tiles would leave compute units
+// idle): 4 wavefronts of 32 x 32 outputs (2 x 2 MFMA blocks), the same LDS
+// layout, loads and split as the 128 x 128 tiles, and the plain schedule of
+// one barrier per K step after the step's MFMAs.
+struct Bf16x3Smem64 {
+  __bf16 a_hi[2][64][XKP];
+  __bf16 a_lo[2][64][XKP];
+  __bf16 b_hi[2][64][XKP];
+  __bf16 b_lo[2][64][XKP];
+};
+
+// MFMAs and the C store of one 64 x 64 tile from the LDS buffers; `stage`
+// (k0, buf) writes the next step's operands into LDS buffer buf.
+template <class Stage, class Load>
+__device__ __forceinline__ void bf16x3_mma64(Bf16x3Smem64& sm, Load&& gload, Stage&& lstore, float* C, int ldc,
+                                             int mrem, int nrem, int64_t K, float alpha) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, lg = lane >> 4;
+  f4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
+  const int64_t nk = (K + XBK - 1) / XBK;
+  if (nk > 0) {
+    gload(0);
+    lstore(0, 0);
+  }
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    const bool more = kt + 1 < nk;
+    if (more) gload((kt + 1) * XBK);
+    bf8_t ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      ah[i] = *(const bf8_t*)&sm.a_hi[cur][wm * 32 + i * 16 + li][8 * lg];
+      al[i] = *(const bf8_t*)&sm.a_lo[cur][wm * 32 + i * 16 + li][8 * lg];
+      bh[i] = *(const bf8_t*)&sm.b_hi[cur][wn * 32 + i * 16 + li][8 * lg];
+      bl[i] = *(const bf8_t*)&sm.b_lo[cur][wn * 32 + i * 16 + li][8 * lg];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+    // the other buffer's readers all passed the previous barrier
+    if (more) lstore(cur ^ 1, (kt + 1) * XBK);
+    __syncthreads();
+  }
+  const __amdgpu_buffer_rsrc_t sc = make_rsrc(C);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wm * 32 + i * 16 + 4 * lg + v;
+        const int c = wn * 32 + j * 16 + li;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, alpha * acc[i][j][v]), sc,
+                                              (r < mrem && c < nrem) ? (r * ldc + c) * 4 : kInvalidOff, 0, 0);
+      }
+}
+
+// 64 x 64 tile of a leaf with split operands (layouts as bf16x3_tile_split).
+__device__ __forceinline__ void bf16x3_tile_split64(Bf16x3Smem64& sm, const __bf16* Ah, const __bf16* Al,
+                                                    const __bf16* Bh, const __bf16* Bl, float* C, int lda,
+                                                    int ldb, int ldc, int mrem, int nrem, int64_t K,
+                                                    float alpha) {
+  const int tid = threadIdx.x;
+  // A: row ar, k group ak; B: k group bg, column bn (one 16-byte group each)
+  const int ar = tid >> 2, ak = tid & 3;
+  const int bg = tid >> 6, bn = tid & 63;
+  const int a_base = (ar * lda + 8 * ak) * 2;
+  const int b_base = bn < nrem ? (bg * ldb + 8 * bn) * 2 : kInvalidOff;
+  u4_t rah, ral, rbh, rbl;
+  auto ld16 = [](__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(u4_t, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  };
+  auto gload = [&](int64_t k0) {
+    const __amdgpu_buffer_rsrc_t sah = make_rsrc(Ah + k0), sal = make_rsrc(Al + k0);
+    const __amdgpu_buffer_rsrc_t sbh = make_rsrc(Bh + (k0 >> 3) * ldb), sbl = make_rsrc(Bl + (k0 >> 3) * ldb);
+    const int ao = (ar < mrem && k0 + 8 * ak < K) ? a_base : kInvalidOff;
+    const int bo = k0 + 8 * bg < K ? b_base : kInvalidOff;
+    rah = ld16(sah, ao);
+    ral = ld16(sal, ao);
+    rbh = ld16(sbh, bo);
+    rbl = ld16(sbl, bo);
+  };
+  auto lstore = [&](int buf, int64_t k0) {
+    if (k0 + XBK > K) {  // last, partial K step (uniform)
+      const int na = (int)(K - k0) - 8 * ak, nb = (int)(K - k0) - 8 * bg;
+      rah = keep_first(rah, na);
+      ral = keep_first(ral, na);
+      rbh = keep_first(rbh, nb);
+      rbl = keep_first(rbl, nb);
+    }
+    *(u4_t*)&sm.a_hi[buf][ar][8 * ak] = rah;
+    *(u4_t*)&sm.a_lo[buf][ar][8 * ak] = ral;
+    *(u4_t*)&sm.b_hi[buf][bn][8 * bg] = rbh;
+    *(u4_t*)&sm.b_lo[buf][bn][8 * bg] = rbl;
+  };
+  bf16x3_mma64(sm, gload, lstore, C, ldc, mrem, nrem, K, alpha);
+}
+
+// 64 x 64 tile with FP32 operands, split on the way into LDS (as bf16x3_tile).
+template <bool PAIR>
+__device__ __forceinline__ void bf16x3_tile64(Bf16x3Smem64& sm, const float* A, const float* B, float* C, int lda,
+                                              int ldb, int ldc, int mrem, int nrem, int64_t K, float alpha) {
+  const int tid = threadIdx.x;
+  // A staging: PAIR: 4 pairs per thread (rows ar + 16 j, k = 2 kp, 2 kp + 1);
+  // otherwise 8 singles (rows ar1 + 8 j, k = ak1).  B: column bn, 8
+  // consecutive k from bk0.
+  const int ar = tid >> 4, kp = tid & 15;
+  const int ar1 = tid >> 5, ak1 = tid & 31;
+  const int bn = tid & 63, bk0 = (tid >> 6) * 8;
+  const int a_step = PAIR ? 16 * lda * 4 : 8 * lda * 4;
+  const int a_base = PAIR ? (ar * lda + 2 * kp) * 4 : (ar1 * lda + ak1) * 4;
+  const int a_rows = PAIR ? (mrem - ar + 15) / 16 : (mrem - ar1 + 7) / 8;
+  const int b_base = bn < nrem ? (bk0 * ldb + bn) * 4 : kInvalidOff;
+  const int b_step = ldb * 4;
+  float ra[8], rb[8];
+  auto gload = [&](int64_t k0) {
+    const __amdgpu_buffer_rsrc_t sa = make_rsrc(A + k0);
+    const __amdgpu_buffer_rsrc_t sb = make_rsrc(B + k0 * (int64_t)ldb);
+    const int kr = K - k0 < XBK ? (int)(K - k0) : XBK;
+    if constexpr (PAIR) {
+      const int av = 2 * kp < kr ? a_base : kInvalidOff;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const f2_t v = __builtin_bit_cast(
+            f2_t, __builtin_amdgcn_raw_buffer_load_b64(sa, j < a_rows ? av : kInvalidOff, j * a_step, 0));
+        ra[2 * j] = v.x;
+        ra[2 * j + 1] = v.y;
+      }
+    } else {
+      const int av = ak1 < kr ? a_base : kInvalidOff;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) ra[j] = load_f32(sa, j < a_rows ? av : kInvalidOff, j * a_step);
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) rb[e] = load_f32(sb, bk0 + e < kr ? b_base : kInvalidOff, e * b_step);
+  };
+  auto lstore = [&](int buf, int64_t) {
+    if constexpr (PAIR) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        __bf16 h0, l0, h1, l1;
+        split(ra[2 * j], h0, l0);
+        split(ra[2 * j + 1], h1, l1);
+        *(bf2_t*)&sm.a_hi[buf][ar + 16 * j][2 * kp] = bf2_t{h0, h1};
+        *(bf2_t*)&sm.a_lo[buf][ar + 16 * j][2 * kp] = bf2_t{l0, l1};
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) split(ra[j], sm.a_hi[buf][ar1 + 8 * j][ak1], sm.a_lo[buf][ar1 + 8 * j][ak1]);
+    }
+    bf8_t h, l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      __bf16 x, y;
+      split(rb[e], x, y);
+      h[e] = x;
+      l[e] = y;
+    }
+    *(bf8_t*)&sm.b_hi[buf][bn][bk0] = h;
+    *(bf8_t*)&sm.b_lo[buf][bn][bk0] = l;
+  };
+  bf16x3_mma64(sm, gload, lstore, C, ldc, mrem, nrem, K, alpha);
+}
+
+template <int TM>
+__global__ void __launch_bounds__(XNT) __attribute__((amdgpu_waves_per_eu(2, TM == 128 ? 2 : 4)))
 gemm_bf16x3_kernel(GemmArgs args) {
   const GemmArgs* ap = kernarg_args();
-  __shared__ Bf16x3Smem sm;
+  using Smem = std::conditional_t<TM == 128, Bf16x3Smem, Bf16x3Smem64>;
+  __shared__ Smem sm;
   const int64_t G = gridDim.x;
   const int64_t slot = (int64_t)(blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
   for (int64_t t = slot; t < ap->total_tiles; t += G) {
@@ -379,48 +558,83 @@ gemm_bf16x3_kernel(GemmArgs args) {
     const char* abase = slot_ptr(ap, job.slot, pr.a, &lda);
     const char* bbase = slot_ptr(ap, job.slot, pr.b, &ldb);
     float* C = (float*)slot_ptr(ap, job.slot, pr.c, &ldc) + pr.c.off;
-    C = uniform_ptr(C + (pr.c.row + job.tm * XBM) * ldc + pr.c.col + job.tn * XBN);
-    const int64_t mr = job.m - job.tm * XBM, nr = job.n - job.tn * XBN;
-    const int mrem = uniform_int(mr < XBM ? (int)mr : XBM);
-    const int nrem = uniform_int(nr < XBN ? (int)nr : XBN);
+    C = uniform_ptr(C + (pr.c.row + job.tm * TM) * ldc + pr.c.col + job.tn * TM);
+    const int64_t mr = job.m - job.tm * TM, nr = job.n - job.tn * TM;
+    const int mrem = uniform_int(mr < TM ? (int)mr : TM);
+    const int nrem = uniform_int(nr < TM ? (int)nr : TM);
     const int ilda = uniform_int((int)lda), ildb = uniform_int((int)ldb), ildc = uniform_int((int)ldc);
     const float alpha = (float)uniform_double(pr.alpha);
     if (uniform_int(pr.a.elt) == ELT_BF16X2) {
       // leaf operands split by the formation kernels (workspace regions, never
       // views): S rows of lda, T k-octets of ldb; offsets in bf16 elements
-      const __bf16* Ah = uniform_ptr((const __bf16*)abase + pr.a.off + job.tm * XBM * lda);
-      const __bf16* Bh = uniform_ptr((const __bf16*)bbase + pr.b.off + job.tn * XBN * 8);
-      bf16x3_tile_split(sm, Ah, uniform_ptr(Ah + pr.a.plane), Bh, uniform_ptr(Bh + pr.b.plane), C, ilda, ildb,
-                        ildc, mrem, nrem, job.k, alpha);
+      const __bf16* Ah = uniform_ptr((const __bf16*)abase + pr.a.off + job.tm * TM * lda);
+      const __bf16* Bh = uniform_ptr((const __bf16*)bbase + pr.b.off + job.tn * TM * 8);
+      if constexpr (TM == 128)
+        bf16x3_tile_split(sm, Ah, uniform_ptr(Ah + pr.a.plane), Bh, uniform_ptr(Bh + pr.b.plane), C, ilda, ildb,
+                          ildc, mrem, nrem, job.k, alpha);
+      else
+        bf16x3_tile_split64(sm, Ah, uniform_ptr(Ah + pr.a.plane), Bh, uniform_ptr(Bh + pr.b.plane), C, ilda,
+                            ildb, ildc, mrem, nrem, job.k, alpha);
       continue;
     }
-    const float* A = uniform_ptr((const float*)abase + pr.a.off + (pr.a.row + job.tm * XBM) * lda + pr.a.col);
-    const float* B = uniform_ptr((const float*)bbase + pr.b.off + pr.b.row * ldb + pr.b.col + job.tn * XBN);
+    const float* A = uniform_ptr((const float*)abase + pr.a.off + (pr.a.row + job.tm * TM) * lda + pr.a.col);
+    const float* B = uniform_ptr((const float*)bbase + pr.b.off + pr.b.row * ldb + pr.b.col + job.tn * TM);
     // even K and 8-byte aligned rows allow pair loads of A
     const bool pair = ((job.k | ilda) & 1) == 0 && (((uintptr_t)A) & 7) == 0;
-    if (pair)
-      bf16x3_tile<true>(sm, A, B, C, ilda, ildb, ildc, mrem, nrem, job.k, alpha);
-    else
-      bf16x3_tile<false>(sm, A, B, C, ilda, ildb, ildc, mrem, nrem, job.k, alpha);
+    if constexpr (TM == 128) {
+      if (pair)
+        bf16x3_tile<true>(sm, A, B, C, ilda, ildb, ildc, mrem, nrem, job.k, alpha);
+      else
+        bf16x3_tile<false>(sm, A, B, C, ilda, ildb, ildc, mrem, nrem, job.k, alpha);
+    } else {
+      if (pair)
+        bf16x3_tile64<true>(sm, A, B, C, ilda, ildb, ildc, mrem, nrem, job.k, alpha);
+      else
+        bf16x3_tile64<false>(sm, A, B, C, ilda, ildb, ildc, mrem, nrem, job.k, alpha);
+    }
   }
 }
 
-hipError_t launch_gemm_bf16x3(const GemmArgs& a, int num_cus, hipStream_t s) {
-  if (a.total_tiles <= 0) return hipSuccess;
+template <int TM>
+static hipError_t launch_bf16x3_tiles(const GemmArgs& a, int num_cus, hipStream_t s) {
+  const GemmArgs* pa = &a;
+  GemmArgs re;
+  if (TM != kTileM) {
+    re = a;
+    int64_t tiles = 0;
+    for (int i = 0; i < re.ngroups; ++i) {
+      GemmGroup& g = re.groups[i];
+      g.tiles_m = (g.m + TM - 1) / TM;
+      g.tiles_n = (g.n + TM - 1) / TM;
+      g.tile_start = tiles;
+      tiles += g.tiles_m * g.tiles_n * g.count;
+    }
+    re.total_tiles = tiles;
+    pa = &re;
+  }
   static std::atomic<int> cached{0};
   int per_cu = cached.load(std::memory_order_relaxed);
   if (!per_cu) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gemm_bf16x3_kernel, XNT, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gemm_bf16x3_kernel<TM>, XNT, 0) != hipSuccess ||
+        per_cu < 1)
       per_cu = 1;
     cached.store(per_cu, std::memory_order_relaxed);
   }
   int64_t G = (int64_t)per_cu * num_cus;
-  const int64_t want = (a.total_tiles + 7) / 8 * 8;
+  const int64_t want = (pa->total_tiles + 7) / 8 * 8;
   if (want < G) G = want;
   if (G < 8) G = 8;
   G = G / 8 * 8;
-  hipLaunchKernelGGL(gemm_bf16x3_kernel, dim3((unsigned)G), dim3(XNT), 0, s, a);
+  hipLaunchKernelGGL(gemm_bf16x3_kernel<TM>, dim3((unsigned)G), dim3(XNT), 0, s, *pa);
   return hipGetLastError();
+}
+
+// Tile edge: an explicit 64 or 128 wins, otherwise 64 when the launch has
+// fewer 128 x 128 tiles than compute units (use_small_tiles).
+hipError_t launch_gemm_bf16x3(const GemmArgs& a, int num_cus, hipStream_t s) {
+  if (a.total_tiles <= 0) return hipSuccess;
+  const bool small = a.tile == 64 || (a.tile != 128 && use_small_tiles(a.total_tiles, num_cus, true));
+  return small ? launch_bf16x3_tiles<64>(a, num_cus, s) : launch_bf16x3_tiles<128>(a, num_cus, s);
 }
 
 }  // namespace fmm

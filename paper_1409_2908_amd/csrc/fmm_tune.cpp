@@ -42,7 +42,7 @@ constexpr int kSlots = 512;            // resident leaf workgroups (2 per comput
 constexpr int kCUs = kSlots / 2;
 constexpr int kSlotsSmall = 4 * kCUs;  // resident 64 x 64 leaf workgroups (4 per compute unit)
 // full-occupancy rate of the 64 x 64 tile relative to the 128 x 128 one
-constexpr double kSmallF64 = 0.93, kSmallF32 = 0.74;
+constexpr double kSmallF64 = 0.93, kSmallF32 = 0.74, kSmallBf16x3 = 0.68;
 constexpr int64_t kMaxLeaves = 60000;  // candidates with more leaves are not offered
 
 // Rate of group g of a plan: on the BF16x3 path the leaf group (the first
@@ -75,16 +75,18 @@ void predict(const PlanSummary& P, int dtype, Candidate& c) {
     return std::ceil(u / (slots * w)) * w * 2.0 * tile_edge * tile_edge / (r / slots);
   };
   double leaf_s = 0;
-  if (tiles > 0 && dtype != 2 && use_small_tiles((int64_t)tiles, kCUs)) {
-    // the launch runs 64 x 64 tiles (FP64 / FP32 only; every group at the
-    // same rate on these paths)
+  if (tiles > 0 && use_small_tiles((int64_t)tiles, kCUs, dtype == 2)) {
+    // the launch runs 64 x 64 tiles (units weighted by each group's rate,
+    // as for the large tiles)
     double units64 = 0, tiles64 = 0;
-    for (const GemmGroup& g : P.groups) {
+    for (size_t i = 0; i < P.groups.size(); ++i) {
+      const GemmGroup& g = P.groups[i];
       const double t = (double)((g.m + 63) / 64) * ((g.n + 63) / 64) * g.count;
-      units64 += t * ((double)g.k + kFix);
+      units64 += t * ((double)g.k + kFix) * ref / rate(dtype, i == 0 && P.levels > 0);
       tiles64 += t;
     }
-    leaf_s = waves_time(units64, wmax, tiles64, kSlotsSmall / kCUs, 64, ref * (dtype == 0 ? kSmallF64 : kSmallF32));
+    const double f = dtype == 0 ? kSmallF64 : dtype == 1 ? kSmallF32 : kSmallBf16x3;
+    leaf_s = waves_time(units64, wmax, tiles64, kSlotsSmall / kCUs, 64, ref * f);
   } else if (tiles > 0) {
     leaf_s = waves_time(units, wmax, tiles, kSlots / kCUs, (double)kTileM, ref);
   }
