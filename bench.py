@@ -198,7 +198,8 @@ def main():
         kernel, peak, tag = f"gemm_kernel<float, {tile}, {tile}>", FP32_PEAK_TFLOPS, f"gemm_f32_t{tile}"
     else:
         # three bf16 products per FP32 product, priced at the bf16 matrix peak
-        kernel, peak, tag = "gemm_bf16x3_kernel", BF16_PEAK_TFLOPS, "gemm_bf16x3"
+        tile = 64 if t128 < cus else 128
+        kernel, peak, tag = f"gemm_bf16x3_kernel<{tile}>", BF16_PEAK_TFLOPS, f"gemm_bf16x3_t{tile}"
         leaf_tflops *= 3
     traffic = traffic_from_profile(tag)
     workload = (f"FP64 square {m}x{k}x{n}, uniform[-1,1)" if dt == F.F64 else
