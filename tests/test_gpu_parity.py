@@ -263,7 +263,7 @@ def test_bench_configuration_sampled_rows(F):
     boundary row against the oracle's row product."""
     import torch
     n = 16384
-    alg, L = os.environ.get("FMM_BENCH_ALG", "strassen_222_7"), int(os.environ.get("FMM_BENCH_LEVELS", "2"))
+    alg, L = os.environ.get("FMM_BENCH_ALG", "fmm_424_26"), int(os.environ.get("FMM_BENCH_LEVELS", "2"))
     say(f"case bench-config {alg} L={L} n={n}")
     A, B = fmm_inputs.operands(0, n, n, n, "uniform")
     with F.Plan(alg, n, n, n, L, F.F64) as p:
@@ -306,3 +306,25 @@ def test_leaf_tile_shapes_agree(F, dtype_name, alg, L, shape):
     assert np.array_equal(out[64].view(iv), out[128].view(iv))
     assert np.array_equal(out[0].view(iv), out[64].view(iv))
 
+
+
+def test_fp64_error_per_depth(F):
+    """The error of each square-configuration base case per depth at 4096^3
+    (uniform inputs; 32 sampled rows, every top-level block boundary among
+    them, against the oracle's row product), printed as a table and held to
+    the FP64 gate."""
+    import torch
+    n = 4096
+    A, B = fmm_inputs.operands(3, n, n, n, "uniform")
+    dA, dB = to_dev(A), to_dev(B)
+    rows = fmm_inputs.sample_rows(2, n, 32, [0, n - 1, n // 2, n // 3, n // 4, 3 * n // 4])
+    ref = classical.gemm_rows(A, B, rows)
+    sel = torch.from_numpy(rows).cuda()
+    for alg in ("strassen_222_7", "fmm_333_23", "fmm_323_15", "fmm_424_26"):
+        errs = []
+        for L in (1, 2, 3):
+            with F.Plan(alg, n, n, n, L, F.F64) as p:
+                got = p.multiply(dA, dB)[sel].cpu().numpy()
+            errs.append(relf(got, ref))
+        say(f"error-per-depth {alg} n={n} L=1/2/3 relF " + " / ".join(f"{e:.2e}" for e in errs))
+        assert max(errs) <= 1e-12, (alg, errs)
