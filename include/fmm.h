@@ -83,8 +83,8 @@ typedef struct {
     double add_bytes;            /* algorithmic bytes moved by the S, T and W stages */
     double gemm_min_bytes;       /* bytes the leaf stage must read and write at least once */
     int fuse_levels;             /* recursion levels formed / combined per addition pass */
-    char alg[32];                /* base case planned ("classical" for a plain GEMM); for
-                                    "auto" the cost model's choice */
+    char alg[80];                /* base case planned ("classical" for a plain GEMM), or one
+                                    per level joined by '+'; for "auto" the model's choice */
     int leaf_tile;               /* leaf tile edge asked for (64 / 128), 0: chosen per launch */
 } fmm_plan_info_t;
 
@@ -109,9 +109,14 @@ typedef struct {
 /* Plan C = A*B for an m x k by k x n product with `levels` recursive steps of
  * the base case `alg` ("classical" for a plain GEMM; "strassen_222_7",
  * "fmm_333_23", "fmm_323_15", "fmm_423_20", "fmm_424_26", "classical_222_8")
- * in dtype `dtype` (fmm_dtype).  The core (m0, k0, n0) is the largest multiple
- * of (M^L, K^L, N^L); the rest is peeled and multiplied classically inside the
- * same grouped launch (Section 3.5).  Allocates the workspace (all R^L leaf
+ * in dtype `dtype` (fmm_dtype).  `alg` may also name one base case per level,
+ * top level first, joined by '+' (e.g. "fmm_424_26+strassen_222_7" with
+ * levels 2: the composition of different base cases across levels of
+ * Section 5.2; the count must equal levels, else FMM_EINVAL; names up to 79
+ * characters; such plans run one level per addition pass).  The core
+ * (m0, k0, n0) is the largest multiple of the product of the levels' (M, K, N)
+ * (M^L, K^L, N^L for one base case); the rest is peeled and multiplied
+ * classically inside the same grouped launch (Section 3.5).  Allocates the workspace (all R^L leaf
  * operands and products live at once, the breadth-first layout of Section 4.2)
  * and the descriptor tables on the current HIP device.  On success *out owns
  * them until fmm_plan_destroy.  Errors: FMM_EINVAL (sizes < 0, levels < 0, a
@@ -234,7 +239,7 @@ const char *fmm_last_error(void);
  * for the exact shape takes precedence (the Python autotuner times the
  * model's best few candidates and records the winner). */
 typedef struct {
-    char alg[32];        /* "classical" or a base-case name */
+    char alg[80];        /* "classical", a base-case name, or one per level joined by '+' */
     int levels;
     int fuse_levels;
     int leaf_tile;       /* leaf tile edge of a recorded choice (64 / 128); 0: chosen per launch */
@@ -303,7 +308,7 @@ typedef struct {
     double launch_ms;    /* when its batch was enqueued */
     double done_ms;      /* when its batch's completion event was seen */
     int batch_size;
-    char alg[32];
+    char alg[80];
     int levels;
 } fmm_completion_t;
 

@@ -181,3 +181,40 @@ def additions(alg: Algorithm) -> int:
     for k in range(alg.M * alg.N):
         cnt += max(0, sum(1 for r in range(alg.R) if alg.W[k][r]) - 1)
     return cnt
+
+
+def compose(a, b):
+    """The bilinear algorithm of two recursion levels, `a` on top and `b`
+    below (Section 5.2 composes base cases across levels): the
+    <a.M b.M, a.K b.K, a.N b.N; a.R b.R> algorithm whose product r = r1 b.R + r2
+    multiplies S_{r1 r2} = sum U_a[i1][r1] U_b[i2][r2] A_{i1 i2} by the
+    corresponding T, where block (x1, x2) of a level-one block x1 is block
+    x1 * (inner count) + x2 in each row and column direction of the composed
+    partition.  Its factor matrices are Kronecker products of a's and b's with
+    the block indices interleaved, so it passes the Brent equations exactly
+    when a and b do."""
+    M, K, N, R = a.M * b.M, a.K * b.K, a.N * b.N, a.R * b.R
+
+    def side(Xa, Xb, rows_a, cols_a, rows_b, cols_b):
+        out = [[0] * R for _ in range(rows_a * rows_b * cols_a * cols_b)]
+        for r1 in range(a.R):
+            for r2 in range(b.R):
+                r = r1 * b.R + r2
+                for i1 in range(rows_a * cols_a):
+                    c1 = Xa[i1][r1]
+                    if c1 == 0:
+                        continue
+                    x1, y1 = divmod(i1, cols_a)
+                    for i2 in range(rows_b * cols_b):
+                        c2 = Xb[i2][r2]
+                        if c2 == 0:
+                            continue
+                        x2, y2 = divmod(i2, cols_b)
+                        row, col = x1 * rows_b + x2, y1 * cols_b + y2
+                        out[row * (cols_a * cols_b) + col][r] = c1 * c2
+        return tuple(tuple(v) for v in out)
+
+    U = side(a.U, b.U, a.M, a.K, b.M, b.K)
+    V = side(a.V, b.V, a.K, a.N, b.K, b.N)
+    W = side(a.W, b.W, a.M, a.N, b.M, b.N)
+    return Algorithm(f"{a.name}+{b.name}", M, K, N, R, U, V, W)

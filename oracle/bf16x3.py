@@ -41,8 +41,9 @@ def gemm(A, B):
 
 
 def fmm(alg, levels, A, B):
-    """C = A @ B by `levels` steps of `alg` with static peeling (peel once to
-    multiples of M^L, K^L, N^L; Section 3.5's fix-ups for the strips) and every
+    """C = A @ B by `levels` steps of `alg` (one base case, or one per level)
+    with static peeling (peel once to multiples of the levels' block counts,
+    M^L, K^L, N^L for one base case; Section 3.5's fix-ups for the strips) and every
     leaf product -- core leaves and peel strips alike -- taken as the emulated
     BF16x3 product of FP32 operands.  Leaf operands are formed in binary64
     (Section 3.1's addition chains) and rounded once to FP32; products are
@@ -54,7 +55,10 @@ def fmm(alg, levels, A, B):
     B = np.asarray(B, dtype=np.float32)
     m, k = A.shape
     n = B.shape[1]
-    fm, fk, fn = alg.M ** levels, alg.K ** levels, alg.N ** levels
+    algs = recursive._levels(alg, levels)  # one base case, or one per level
+    fm = int(np.prod([a.M for a in algs])) if algs else 1
+    fk = int(np.prod([a.K for a in algs])) if algs else 1
+    fn = int(np.prod([a.N for a in algs])) if algs else 1
     m0, k0, n0 = fm * (m // fm), fk * (k // fk), fn * (n // fn)
     C = np.zeros((m, n), dtype=np.float64)
     if m0 and k0 and n0:

@@ -82,6 +82,16 @@ def chain(coeffs, blocks, counter=None):
     return acc
 
 
+def _levels(alg, levels):
+    """The base case of every level, top first: `alg` is one algorithm (used at
+    every level) or a sequence with one per level (Section 5.2 composes
+    different base cases across levels)."""
+    if isinstance(alg, (list, tuple)):
+        assert len(alg) == levels, (len(alg), levels)
+        return list(alg)
+    return [alg] * levels
+
+
 def _split(X, rows, cols):
     """Blocks of X (already trimmed to multiples) in row-wise order."""
     h = X.shape[0] // rows
@@ -125,39 +135,43 @@ def _fixups(A, B, C, m0, k0, n0, counter):
 
 
 def fmm(alg, levels, A, B, peel="dynamic", counter=None):
-    """C = A @ B by `levels` recursive steps of `alg`, classical leaves."""
+    """C = A @ B by `levels` recursive steps of `alg` (one base case, or one
+    per level, top first), classical leaves."""
     A = np.asarray(A)
     B = np.asarray(B)
     m, k = A.shape
     assert B.shape[0] == k
     n = B.shape[1]
-    M, K, N = alg.M, alg.K, alg.N
+    algs = _levels(alg, levels)
     dt = np.result_type(A.dtype, B.dtype)
     if peel == "dynamic":
-        if levels == 0 or m < M or k < K or n < N:
+        if levels == 0 or m < algs[0].M or k < algs[0].K or n < algs[0].N:
             return _leaf(A, B, counter)
+        M, K, N = algs[0].M, algs[0].K, algs[0].N
         m0, k0, n0 = M * (m // M), K * (k // K), N * (n // N)
         C = np.zeros((m, n), dtype=dt) if dt != object else np.full((m, n), 0, dtype=object)
-        C[:m0, :n0] = _one_level(alg, A[:m0, :k0], B[:k0, :n0],
-                                 lambda S, T: fmm(alg, levels - 1, S, T, "dynamic", counter),
+        C[:m0, :n0] = _one_level(algs[0], A[:m0, :k0], B[:k0, :n0],
+                                 lambda S, T: fmm(algs[1:], levels - 1, S, T, "dynamic", counter),
                                  counter)
         return _fixups(A, B, C, m0, k0, n0, counter)
     if peel == "static":
-        fm, fk, fn = M ** levels, K ** levels, N ** levels
+        fm = int(np.prod([a.M for a in algs])) if algs else 1
+        fk = int(np.prod([a.K for a in algs])) if algs else 1
+        fn = int(np.prod([a.N for a in algs])) if algs else 1
         m0, k0, n0 = fm * (m // fm), fk * (k // fk), fn * (n // fn)
         C = np.zeros((m, n), dtype=dt) if dt != object else np.full((m, n), 0, dtype=object)
         if m0 and k0 and n0:
-            C[:m0, :n0] = _core(alg, levels, A[:m0, :k0], B[:k0, :n0], counter)
+            C[:m0, :n0] = _core(algs, levels, A[:m0, :k0], B[:k0, :n0], counter)
         elif m0 and n0:
             C[:m0, :n0] = 0
         return _fixups(A, B, C, m0, k0, n0, counter)
     raise ValueError(peel)
 
 
-def _core(alg, levels, A, B, counter):
+def _core(algs, levels, A, B, counter):
     if levels == 0:
         return _leaf(A, B, counter)
-    return _one_level(alg, A, B, lambda S, T: _core(alg, levels - 1, S, T, counter), counter)
+    return _one_level(algs[0], A, B, lambda S, T: _core(algs[1:], levels - 1, S, T, counter), counter)
 
 
 def form_operands(alg, levels, X, which):
@@ -165,15 +179,15 @@ def form_operands(alg, levels, X, which):
     in leaf order rho = (rho_1, ..., rho_L) (rho_1 most significant): the
     S_rho (which='A', coefficients from U) or T_rho (which='B', from V),
     each formed level by level with `chain`.  Used to check operand-formation
-    kernels bit for bit."""
-    rows, cols = (alg.M, alg.K) if which == "A" else (alg.K, alg.N)
-    coef = alg.U if which == "A" else alg.V
+    kernels bit for bit.  `alg` is one base case or one per level."""
     cur = [X]
-    for _ in range(levels):
+    for a in _levels(alg, levels):
+        rows, cols = (a.M, a.K) if which == "A" else (a.K, a.N)
+        coef = a.U if which == "A" else a.V
         nxt = []
         for Y in cur:
             blocks = _split(Y, rows, cols)
-            for r in range(alg.R):
+            for r in range(a.R):
                 nxt.append(chain([coef[i][r] for i in range(rows * cols)], blocks))
         cur = nxt
     return cur
@@ -182,17 +196,18 @@ def form_operands(alg, levels, X, which):
 def combine_products(alg, levels, Ms):
     """C from the R^L leaf products (leaf order as in form_operands), deepest
     level first, each level with `chain` over the rows of W: the order the
-    recursion of Section 3.1 produces."""
+    recursion of Section 3.1 produces.  `alg` is one base case or one per
+    level (top first)."""
     cur = list(Ms)
-    for _ in range(levels):
+    for al in reversed(_levels(alg, levels)):
         nxt = []
-        for g in range(len(cur) // alg.R):
-            group = cur[g * alg.R:(g + 1) * alg.R]
+        for g in range(len(cur) // al.R):
+            group = cur[g * al.R:(g + 1) * al.R]
             h, w = group[0].shape
-            C = np.empty((alg.M * h, alg.N * w), dtype=group[0].dtype)
-            for a in range(alg.M):
-                for c in range(alg.N):
-                    C[a * h:(a + 1) * h, c * w:(c + 1) * w] = chain(list(alg.W[a * alg.N + c]), group)
+            C = np.empty((al.M * h, al.N * w), dtype=group[0].dtype)
+            for a in range(al.M):
+                for c in range(al.N):
+                    C[a * h:(a + 1) * h, c * w:(c + 1) * w] = chain(list(al.W[a * al.N + c]), group)
             nxt.append(C)
         cur = nxt
     return cur[0]

@@ -48,7 +48,7 @@ class _Info(ctypes.Structure):
                 ("gemm_tiles", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t),
                 ("leaf_flops", ctypes.c_double), ("classical_flops", ctypes.c_double),
                 ("add_bytes", ctypes.c_double), ("gemm_min_bytes", ctypes.c_double),
-                ("fuse_levels", ctypes.c_int), ("alg", ctypes.c_char * 32), ("leaf_tile", ctypes.c_int)]
+                ("fuse_levels", ctypes.c_int), ("alg", ctypes.c_char * 80), ("leaf_tile", ctypes.c_int)]
 
 
 class _Options(ctypes.Structure):
@@ -58,7 +58,7 @@ class _Options(ctypes.Structure):
 
 
 class _Candidate(ctypes.Structure):
-    _fields_ = [("alg", ctypes.c_char * 32), ("levels", ctypes.c_int), ("fuse_levels", ctypes.c_int),
+    _fields_ = [("alg", ctypes.c_char * 80), ("levels", ctypes.c_int), ("fuse_levels", ctypes.c_int),
                 ("leaf_tile", ctypes.c_int), ("model_ms", ctypes.c_double), ("leaf_ms", ctypes.c_double), ("add_ms", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_size_t)]
 
@@ -80,7 +80,7 @@ class _Completion(ctypes.Structure):
     _fields_ = [("id", ctypes.c_int64), ("user", ctypes.c_void_p), ("status", ctypes.c_int),
                 ("submit_ms", ctypes.c_double), ("launch_ms", ctypes.c_double),
                 ("done_ms", ctypes.c_double), ("batch_size", ctypes.c_int),
-                ("alg", ctypes.c_char * 32), ("levels", ctypes.c_int)]
+                ("alg", ctypes.c_char * 80), ("levels", ctypes.c_int)]
 
 
 def _load():

@@ -147,7 +147,7 @@ hipError_t run_form(const fmm::Plan& P, const std::vector<fmm::FormPass>& passes
     a.out_plane = fp.out_plane;
     a.out_elt = fp.out_elt;
     a.nout = fp.nout;
-    hipError_t e = fmm::launch_form(P.alg_id, a, fp.side, fp.lv, fp.ngroups, s);
+    hipError_t e = fmm::launch_form(fp.alg, a, fp.side, fp.lv, fp.ngroups, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -191,10 +191,10 @@ hipError_t run_combine(const fmm::Plan& P, const fmm::Bases& b, hipStream_t s) {
     a.in_elt = cp.in_elt;
     a.has_p = cp.has_p ? 1 : 0;
     a.p = cp.p;
-    const fmm::AlgInfo& A = fmm::alg_info(P.alg_id);
+    const fmm::AlgInfo& A = fmm::alg_info(cp.alg);
     for (int k = 0; k < A.M * A.N; ++k)
       for (int r = 0; r < A.R; ++r) a.wc[k][r] = A.W[k * A.R + r];
-    hipError_t e = fmm::launch_combine(P.alg_id, a, cp.lv, cp.ngroups, s);
+    hipError_t e = fmm::launch_combine(cp.alg, a, cp.lv, cp.ngroups, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -615,7 +615,10 @@ fmm_status fmm_plan_info(fmm_plan_t p, fmm_plan_info_t* info) {
   info->add_bytes = P.add_bytes;
   info->fuse_levels = P.levels > 0 ? P.fuse : 0;
   info->gemm_min_bytes = P.gemm_min_bytes;
-  std::snprintf(info->alg, sizeof(info->alg), "%s", P.alg_id < 0 ? "classical" : fmm::alg_info(P.alg_id).name);
+  // one base case per level joined by '+' when the levels differ
+  const bool mixed = P.alg_name.find('+') != std::string::npos;
+  std::snprintf(info->alg, sizeof(info->alg), "%s",
+                P.alg_id < 0 ? "classical" : mixed ? P.alg_name.c_str() : fmm::alg_info(P.alg_id).name);
   info->leaf_tile = P.leaf_tile;
   return FMM_OK;
 }
@@ -742,7 +745,13 @@ fmm_status fmm_tune_record(int64_t m, int64_t k, int64_t n, int dtype, const cha
   if (m < 0 || k < 0 || n < 0) return fail(FMM_EINVAL, "sizes must be non-negative");
   if (dtype < 0 || dtype > 2) return fail(FMM_EINVAL, "unknown dtype");
   if (!alg) return fail(FMM_EINVAL, "alg is NULL");
-  if (fmm::find_algorithm(alg) == -2) return fail(FMM_EALG, std::string("unknown algorithm '") + alg + "'");
+  if (std::strlen(alg) >= sizeof(fmm::Candidate::alg)) return fail(FMM_EINVAL, "algorithm name too long");
+  {
+    std::vector<int> ids;
+    std::string err;
+    const int pr = fmm::parse_levels(alg, levels, &ids, &err);
+    if (pr > 0) return fail((fmm_status)pr, err);
+  }
   if (levels < 0 || fuse_levels < 0 || fuse_levels > 2) return fail(FMM_EINVAL, "bad levels or fuse_levels");
   if (leaf_tile != 0 && leaf_tile != 64 && leaf_tile != 128) return fail(FMM_EINVAL, "leaf_tile must be 0, 64 or 128");
   fmm::Plan P;

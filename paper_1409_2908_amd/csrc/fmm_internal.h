@@ -50,6 +50,7 @@ struct Bases {
 //   sum over the lv-level Kronecker product of the side's coefficient matrix
 //   applied to the (BR*BC)^lv blocks of the group's source at position (p, q).
 struct FormPass {
+  int alg = -1;   // base case of the pass's levels
   int side;       // 0: A side (U, blocks M x K); 1: B side (V, blocks K x N)
   int lv;         // levels fused in this pass (1 or 2)
   int depth_in;   // depth of the sources (0 = the input matrix)
@@ -69,6 +70,7 @@ struct FormPass {
 // matrix of (BR^lv h) x (BC^lv w) through `out`.  The last pass (depth 0)
 // writes C and adds the k-peel product P when present.
 struct CombinePass {
+  int alg = -1;   // base case of the pass's levels
   int lv;
   int depth_in;
   int64_t h, w;
@@ -146,7 +148,9 @@ struct LeafRef {
 };
 
 struct Plan {
-  int alg_id = -1;  // -1: classical (no recursion)
+  int alg_id = -1;  // -1: classical (no recursion); else the top level's base case
+  std::vector<int> lv_alg;  // base case of every level, top first
+  std::string alg_name;     // "classical", a base case, or one base case per level joined by '+'
   int M = 1, K = 1, N = 1, R = 1;
   int64_t m = 0, k = 0, n = 0;
   int levels = 0;
@@ -193,6 +197,13 @@ std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n,
 
 int find_algorithm(const char* name);  // -1 for "classical", -2 unknown
 
+// Base case of every recursion level, top first.  `alg` names one base case
+// (used at every level) or one per level joined by '+' (Section 5.2 composes
+// different base cases across levels; their count must equal `levels`).
+// Returns -1 for "classical" (ids empty), 0 with `levels` ids, or an error
+// status (FMM_EALG unknown name, FMM_EINVAL malformed list) with *err set.
+int parse_levels(const char* alg, int levels, std::vector<int>* ids, std::string* err);
+
 // What make_plan would produce, without its R^L descriptors: the GEMM groups
 // (tiles filled in), the addition bytes, the workspace bytes and the pass
 // counts, computed per pass from view counts in O(levels).  Equal to the
@@ -212,7 +223,7 @@ int set_error(int code, const std::string& msg);
 
 // One candidate of the cost model (fmm_tune.cpp).
 struct Candidate {
-  char alg[32];
+  char alg[80];
   int levels = 0;
   int fuse = 0;
   int tile = 0;  // leaf tile edge of a recorded choice; 0: chosen per launch

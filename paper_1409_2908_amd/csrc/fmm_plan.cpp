@@ -51,7 +51,10 @@ int col_nnz(const signed char* X, int rows, int R, int r, int* where, int* coef)
 // bytes: the level-one intermediates are never written), except for BF16x3
 // plans of wide base cases (R > 8), whose split T operands in k-octets are
 // formed by the register kernel, which measured slower fused than unfused.
-int resolve_fuse(int requested, int R, int dtype) {
+// Plans whose levels use different base cases always run one level per pass.
+int resolve_fuse(int requested, int R, int dtype, const std::vector<int>& ids) {
+  for (int id : ids)
+    if (id != ids[0]) return 1;  // levels of different base cases: one level per pass
   if (requested == 1 || requested == 2) return requested;
   const char* e = std::getenv("FMM_FUSE");
   if (e && (e[0] == '1' || e[0] == '2') && e[1] == 0) return e[0] - '0';
@@ -72,6 +75,26 @@ std::vector<int> schedule(int L, int fuse, bool top_down) {
     rest -= lv;
   }
   return s;
+}
+
+// Passes of a plan whose levels use the base cases `ids`: as schedule() when
+// every level uses the same one, else one level per pass (a fused pass needs
+// one base case for both of its levels).
+std::vector<int> schedule_ids(const std::vector<int>& ids, int fuse, bool top_down) {
+  for (int id : ids)
+    if (id != ids[0]) return std::vector<int>(ids.size(), 1);
+  return schedule((int)ids.size(), fuse, top_down);
+}
+
+// Products of a per-level dimension over the first d levels, d = 0..L.
+std::vector<int64_t> prefix(const std::vector<int>& ids, int which) {
+  std::vector<int64_t> p(ids.size() + 1, 1);
+  for (size_t l = 0; l < ids.size(); ++l) {
+    const AlgInfo& A = alg_info(ids[l]);
+    const int v = which == 0 ? A.M : which == 1 ? A.K : which == 2 ? A.N : A.R;
+    p[l + 1] = p[l] * v;
+  }
+  return p;
 }
 
 // Layout of a split (BF16x3) leaf operand of h x w elements: S (side 0)
@@ -95,12 +118,8 @@ struct Node {
 // Builds the operand-formation passes of one side.  Returns leaf refs.
 std::vector<Ref> plan_side(Plan& P, int side, Arena& ws, std::vector<FormPass>& passes,
                            int64_t* materialized, double* bytes) {
-  const AlgInfo& A = alg_info(P.alg_id);
-  const int BR = side == 0 ? A.M : A.K;
-  const int BC = side == 0 ? A.K : A.N;
-  const int NB = BR * BC;
-  const int R = A.R;
-  const signed char* coef = side == 0 ? A.U : A.V;
+  const std::vector<int64_t> rdiv = prefix(P.lv_alg, side == 0 ? 0 : 1);
+  const std::vector<int64_t> cdiv = prefix(P.lv_alg, side == 0 ? 1 : 2);
   const int64_t rows0 = side == 0 ? P.m0 : P.k0;
   const int64_t cols0 = side == 0 ? P.k0 : P.n0;
   const int in_elt = P.elt;
@@ -109,17 +128,23 @@ std::vector<Ref> plan_side(Plan& P, int side, Arena& ws, std::vector<FormPass>& 
   nodes[0] = Ref{side == 0 ? BUF_A : BUF_B, in_elt, 0, 0, 0, 0, 1.0};
   int depth = 0;
   *materialized = 0;
-  for (int lv : schedule(P.levels, P.fuse, true)) {
+  for (int lv : schedule_ids(P.lv_alg, P.fuse, true)) {
+    const AlgInfo& A = alg_info(P.lv_alg[depth]);  // every level of a fused pass uses it
+    const int BC = side == 0 ? A.K : A.N;
+    const int NB = (side == 0 ? A.M : A.K) * BC;
+    const int R = A.R;
+    const signed char* coef = side == 0 ? A.U : A.V;
     const int d2 = depth + lv;
     const bool final_pass = d2 == P.levels;
     // the BF16x3 path writes its leaf operands split (hi / lo planes)
     const bool split = final_pass && P.dtype == 2;
     FormPass fp;
+    fp.alg = P.lv_alg[depth];
     fp.side = side;
     fp.lv = lv;
     fp.depth_in = depth;
-    fp.h = rows0 / ipow(BR, d2);
-    fp.w = cols0 / ipow(BC, d2);
+    fp.h = rows0 / rdiv[d2];
+    fp.w = cols0 / cdiv[d2];
     fp.out_ld = round_up(fp.w, 16);
     fp.out_elt = split ? ELT_BF16X2 : final_pass ? P.elt : ELT_F64;
     fp.ngroups = (int)nodes.size();
@@ -152,8 +177,8 @@ std::vector<Ref> plan_side(Plan& P, int side, Arena& ws, std::vector<FormPass>& 
             break;
           }
           alpha *= c;
-          const int64_t bh = rows0 / ipow(BR, depth + j + 1);
-          const int64_t bw = cols0 / ipow(BC, depth + j + 1);
+          const int64_t bh = rows0 / rdiv[depth + j + 1];
+          const int64_t bw = cols0 / cdiv[depth + j + 1];
           row += (int64_t)(where / BC) * bh;
           col += (int64_t)(where % BC) * bw;
         }
@@ -211,20 +236,22 @@ int single_columns(const signed char* X, int rows, int R) {
   return cnt;
 }
 
-void summarize_side(const AlgInfo& A, int side, int levels, int fuse, int dtype, int elt, int64_t rows0,
+void summarize_side(const std::vector<int>& ids, int side, int fuse, int dtype, int elt, int64_t rows0,
                     int64_t cols0, ArenaSim& ws, double* bytes, int* passes) {
-  const int BR = side == 0 ? A.M : A.K;
-  const int BC = side == 0 ? A.K : A.N;
-  const int NB = BR * BC;
-  const int64_t ns = single_columns(side == 0 ? A.U : A.V, NB, A.R);
+  const int levels = (int)ids.size();
+  const std::vector<int64_t> rdiv = prefix(ids, side == 0 ? 0 : 1);
+  const std::vector<int64_t> cdiv = prefix(ids, side == 0 ? 1 : 2);
   // groups whose element type is the path's, and FP64 groups of an FP32 path
   int64_t g_in = 1, g_f64 = 0;
   int depth = 0;
-  for (int lv : schedule(levels, fuse, true)) {
+  for (int lv : schedule_ids(ids, fuse, true)) {
+    const AlgInfo& A = alg_info(ids[depth]);
+    const int NB = (side == 0 ? A.M : A.K) * (side == 0 ? A.K : A.N);
+    const int64_t ns = single_columns(side == 0 ? A.U : A.V, NB, A.R);
     const int d2 = depth + lv;
     const bool final_pass = d2 == levels;
     const bool split = final_pass && dtype == 2;
-    const int64_t h = rows0 / ipow(BR, d2), w = cols0 / ipow(BC, d2);
+    const int64_t h = rows0 / rdiv[d2], w = cols0 / cdiv[d2];
     const int out_elt = final_pass ? elt : ELT_F64;
     const int64_t nout = ipow(A.R, lv), nv = split ? 0 : ipow(ns, lv);
     // reads: every group reads NB^lv blocks of its element type
@@ -265,26 +292,28 @@ std::string summarize_plan(PlanSummary& S, const char* alg, int64_t m, int64_t k
   if (m < 0 || k < 0 || n < 0) return "sizes must be non-negative";
   if (levels < 0 || levels > 6) return "levels must be in [0, 6]";
   if (dtype < 0 || dtype > 2) return "unknown dtype";
-  const int id = find_algorithm(alg);
-  if (id == -2) return std::string("unknown algorithm '") + (alg ? alg : "(null)") + "'";
+  std::vector<int> ids;
+  std::string err;
+  const int pr = parse_levels(alg, levels, &ids, &err);
+  if (pr > 0) return err;
   const int elt = dtype == 0 ? ELT_F64 : ELT_F32;
   const size_t es = elt_size(elt);
-  int L = id < 0 ? 0 : levels;
+  int L = pr < 0 ? 0 : levels;
   if (m == 0 || n == 0 || k == 0) L = 0;
   S.levels = L;
   if (L == 0) {
     if (m > 0 && n > 0) S.groups.push_back(GemmGroup{m, n, k, 1, 0, 0, 0, 0});
   } else {
-    const AlgInfo& A = alg_info(id);
-    S.fuse = resolve_fuse(fuse, A.R, dtype);
-    const int64_t fm = ipow(A.M, L), fk = ipow(A.K, L), fn = ipow(A.N, L);
+    S.fuse = resolve_fuse(fuse, alg_info(ids[0]).R, dtype, ids);
+    const std::vector<int64_t> pm = prefix(ids, 0), pk = prefix(ids, 1), pn = prefix(ids, 2), prr = prefix(ids, 3);
+    const int64_t fm = pm[L], fk = pk[L], fn = pn[L];
     const int64_t m0 = m / fm * fm, k0 = k / fk * fk, n0 = n / fn * fn;
     const int64_t ml = m0 / fm, kl = k0 / fk, nl = n0 / fn;
     if (ml < 1 || kl < 1 || nl < 1) return "recursion depth leaves a leaf dimension < 1";
     ArenaSim ws;
-    summarize_side(A, 0, L, S.fuse, dtype, elt, m0, k0, ws, &S.add_bytes, &S.form_passes);
-    summarize_side(A, 1, L, S.fuse, dtype, elt, k0, n0, ws, &S.add_bytes, &S.form_passes);
-    const int64_t nleaves = ipow(A.R, L);
+    summarize_side(ids, 0, S.fuse, dtype, elt, m0, k0, ws, &S.add_bytes, &S.form_passes);
+    summarize_side(ids, 1, S.fuse, dtype, elt, k0, n0, ws, &S.add_bytes, &S.form_passes);
+    const int64_t nleaves = prr[L];
     const int64_t m_ld = round_up(nl, 16);
     const int64_t m_stride = round_up(ml * m_ld * (int64_t)es, 256) / (int64_t)es;
     ws.alloc_many(1, (size_t)m_stride * es * nleaves);
@@ -298,12 +327,12 @@ std::string summarize_plan(PlanSummary& S, const char* alg, int64_t m, int64_t k
     if (m0 < m) S.groups.push_back(GemmGroup{m - m0, n, k, 1, 0, 0, 0, 0});
     int depth = L;
     size_t node_es = es;
-    for (int lv : schedule(L, S.fuse, false)) {
+    for (int lv : schedule_ids(ids, S.fuse, false)) {
       const int d2 = depth - lv;
-      const int64_t h = m0 / ipow(A.M, depth), w = n0 / ipow(A.N, depth);
-      const int64_t ngroups = ipow(A.R, d2), per = ipow(A.R, lv);
+      const int64_t h = m0 / pm[depth], w = n0 / pn[depth];
+      const int64_t ngroups = prr[d2], per = prr[depth] / prr[d2];
       S.add_bytes += (double)ngroups * per * h * w * node_es;
-      const int64_t oh = h * ipow(A.M, lv), ow = w * ipow(A.N, lv);
+      const int64_t oh = h * (pm[depth] / pm[d2]), ow = w * (pn[depth] / pn[d2]);
       if (d2 == 0) {
         if (has_p) S.add_bytes += (double)m0 * n0 * es;
         S.add_bytes += (double)m0 * n0 * es;
@@ -334,6 +363,50 @@ int find_algorithm(const char* name) {
   return -2;
 }
 
+int parse_levels(const char* alg, int levels, std::vector<int>* ids, std::string* err) {
+  ids->clear();
+  if (!alg) {
+    *err = "unknown algorithm '(null)'";
+    return 5;  // FMM_EALG
+  }
+  if (std::strlen(alg) >= 80) {
+    *err = "algorithm name longer than 79 characters";
+    return 1;  // FMM_EINVAL
+  }
+  if (!std::strchr(alg, '+')) {
+    const int id = find_algorithm(alg);
+    if (id == -2) {
+      *err = std::string("unknown algorithm '") + alg + "'";
+      return 5;
+    }
+    if (id == -1) return -1;
+    ids->assign(levels > 0 ? levels : 0, id);
+    return 0;
+  }
+  std::string part;
+  for (const char* c = alg;; ++c) {
+    if (*c == '+' || *c == 0) {
+      const int id = find_algorithm(part.c_str());
+      if (id < 0) {
+        *err = "'" + part + "' in '" + alg + "' is not a base case";
+        return 5;
+      }
+      ids->push_back(id);
+      part.clear();
+      if (*c == 0) break;
+    } else {
+      part += *c;
+    }
+  }
+  if ((int)ids->size() != levels) {
+    *err = std::string("'") + alg + "' names " + std::to_string(ids->size()) +
+           " levels; levels must equal that count";
+    ids->clear();
+    return 1;  // FMM_EINVAL
+  }
+  return 0;
+}
+
 std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
                       int dtype, int fuse, int* code) {
   *code = 1;  // FMM_EINVAL
@@ -341,12 +414,16 @@ std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n,
   if (levels < 0 || levels > 6) return "levels must be in [0, 6]";
   if (dtype < 0 || dtype > 2) return "unknown dtype";
   if (fuse < 0 || fuse > 2) return "fuse must be 0 (default), 1 or 2";
-  const int id = find_algorithm(alg);
-  if (id == -2) {
-    *code = 5;  // FMM_EALG
-    return std::string("unknown algorithm '") + (alg ? alg : "(null)") + "'";
+  std::vector<int> ids;
+  std::string perr;
+  const int pr = parse_levels(alg, levels, &ids, &perr);
+  if (pr > 0) {
+    *code = pr;
+    return perr;
   }
+  const int id = pr < 0 ? -1 : ids.empty() ? find_algorithm(alg) : ids[0];
   P = Plan();
+  P.alg_name = alg;
   P.m = m;
   P.k = k;
   P.n = n;
@@ -358,12 +435,13 @@ std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n,
   if (m == 0 || n == 0 || k == 0) P.levels = 0;  // nothing to recurse on
   if (P.levels > 0) {
     const AlgInfo& A = alg_info(id);
+    P.lv_alg = ids;
     P.M = A.M;
     P.K = A.K;
     P.N = A.N;
     P.R = A.R;
-    P.fuse = resolve_fuse(fuse, A.R, dtype);
-    const int64_t fm = ipow(A.M, P.levels), fk = ipow(A.K, P.levels), fn = ipow(A.N, P.levels);
+    P.fuse = resolve_fuse(fuse, A.R, dtype, ids);
+    const int64_t fm = prefix(ids, 0)[P.levels], fk = prefix(ids, 1)[P.levels], fn = prefix(ids, 2)[P.levels];
     P.m0 = m / fm * fm;
     P.k0 = k / fk * fk;
     P.n0 = n / fn * fn;
@@ -388,10 +466,11 @@ std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n,
   const Ref refC{BUF_C, P.elt, 0, 0, 0, 0, 1.0};
 
   if (P.levels > 0) {
-    const int L = P.levels, R = P.R;
+    const int L = P.levels;
+    const std::vector<int64_t> pm = prefix(P.lv_alg, 0), pn = prefix(P.lv_alg, 2), prr = prefix(P.lv_alg, 3);
     std::vector<Ref> S = plan_side(P, 0, ws, P.s_passes, &P.s_mat, &add_bytes);
     std::vector<Ref> T = plan_side(P, 1, ws, P.t_passes, &P.t_mat, &add_bytes);
-    const int64_t nleaves = ipow(R, L);
+    const int64_t nleaves = prr[L];
     // Leaf products M_rho, contiguous with a uniform stride.
     const int64_t m_ld = round_up(P.nl, 16);
     const int64_t m_stride = round_up(P.ml * m_ld * (int64_t)es, 256) / (int64_t)es;
@@ -455,23 +534,24 @@ std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n,
     int64_t node_stride = m_stride, node_ld = m_ld;
     int node_elt = P.elt;
     int depth = L;
-    std::vector<int> sched = schedule(L, P.fuse, false);
+    std::vector<int> sched = schedule_ids(P.lv_alg, P.fuse, false);
     for (size_t pi = 0; pi < sched.size(); ++pi) {
       const int lv = sched[pi];
       const int d2 = depth - lv;
       CombinePass cp;
+      cp.alg = P.lv_alg[d2];  // every level of a fused pass uses it
       cp.lv = lv;
       cp.depth_in = depth;
-      cp.h = P.m0 / ipow(P.M, depth);
-      cp.w = P.n0 / ipow(P.N, depth);
+      cp.h = P.m0 / pm[depth];
+      cp.w = P.n0 / pn[depth];
       cp.in_elt = node_elt;
       cp.in_ld = node_ld;
       cp.in_stride = node_stride;
-      const int64_t ngroups = ipow(R, d2);
-      const int64_t per = ipow(R, lv);
+      const int64_t ngroups = prr[d2];
+      const int64_t per = prr[depth] / prr[d2];
       cp.ngroups = (int)ngroups;
       add_bytes += (double)ngroups * per * cp.h * cp.w * elt_size(node_elt);
-      const int64_t oh = cp.h * ipow(P.M, lv), ow = cp.w * ipow(P.N, lv);
+      const int64_t oh = cp.h * (pm[depth] / pm[d2]), ow = cp.w * (pn[depth] / pn[d2]);
       std::vector<int64_t> next_off;
       if (d2 == 0) {
         cp.in_off.push_back(node_off[0]);

@@ -120,11 +120,12 @@ std::string rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const ch
   if (dtype < 0 || dtype > 2) return "unknown dtype";
   if (!budget) budget = default_budget();
   const bool any = !alg || !std::strcmp(alg, "auto");
+  const bool listed = !any && std::strchr(alg, '+');  // one base case per level
   std::vector<int> ids;
   if (any) {
     for (int i = 0; i < kNumAlgorithms; ++i)
       if (std::strcmp(alg_info(i).name, "classical_222_8")) ids.push_back(i);
-  } else {
+  } else if (!listed) {
     const int id = find_algorithm(alg);
     if (id == -2) return std::string("unknown algorithm '") + alg + "'";
     if (id >= 0) ids.push_back(id);
@@ -140,7 +141,26 @@ std::string rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const ch
     predict(P, dtype, c);
     out.push_back(c);
   };
-  if (any || find_algorithm(alg) == -1) add("classical", 0);
+  if (listed) {
+    std::vector<int> lv;
+    std::string err;
+    const int count = (int)std::count(alg, alg + std::strlen(alg), '+') + 1;
+    if (parse_levels(alg, count, &lv, &err) > 0) return err;
+    add(alg, count);
+  }
+  if (any || (!listed && find_algorithm(alg) == -1)) add("classical", 0);
+  if (any) {
+    // two levels of different base cases (Section 5.2's composition), when
+    // every leaf dimension keeps 64 or more
+    for (int a : ids)
+      for (int b : ids) {
+        if (a == b) continue;
+        const AlgInfo &A = alg_info(a), &B = alg_info(b);
+        if (m / (A.M * B.M) < 64 || k / (A.K * B.K) < 64 || n / (A.N * B.N) < 64) continue;
+        const std::string name = std::string(A.name) + "+" + B.name;
+        add(name.c_str(), 2);
+      }
+  }
   for (int id : ids) {
     const AlgInfo& a = alg_info(id);
     if (!any) add(a.name, 0);  // depth 0 of a named base case: the classical product

@@ -195,3 +195,26 @@ def test_bf16x3_leaf_tile_shapes_agree(F, alg, L, shape):
         assert relf(out[tile], emu) <= 2e-6 * 2 ** max(L, 1), tile
     assert np.array_equal(out[64].view(np.int32), out[128].view(np.int32))
     assert np.array_equal(out[0].view(np.int32), out[64].view(np.int32))
+
+
+
+@pytest.mark.parametrize("spec,names", [("fmm_424_26+strassen_222_7", ["fmm_424_26", "strassen_222_7"]),
+                                        ("strassen_222_7+fmm_333_23", ["strassen_222_7", "fmm_333_23"])])
+@pytest.mark.parametrize("dtype_name", ["F32_BF16X3", "F32"])
+def test_fp32_mixed_levels_parity(F, spec, names, dtype_name):
+    """One base case per level on the FP32 paths: BF16x3 against the emulated
+    mixed algorithm, plain FP32 against the binary64 product."""
+    algs = [algorithms.get(x) for x in names]
+    fm = int(np.prod([a.M for a in algs]))
+    fk = int(np.prod([a.K for a in algs]))
+    fn = int(np.prod([a.N for a in algs]))
+    m, k, n = fm * 5 + 1, fk * 3 + 2, fn * 4 + 1
+    say(f"case fp32 mixed {dtype_name} {spec} m={m} k={k} n={n}")
+    A, B = fmm_inputs.operands(29, m, k, n, "normal_rowscaled", np.float32)
+    C = _run(F, spec, 2, A, B, getattr(F, dtype_name))
+    if dtype_name == "F32_BF16X3":
+        e = relf(C, bf16x3.fmm(algs, 2, A, B))
+    else:
+        e = relf(C, classical.gemm(A, B))
+    say(f"  relF={e:.2e}")
+    assert e <= 2e-6 * 4

@@ -328,3 +328,68 @@ def test_fp64_error_per_depth(F):
             errs.append(relf(got, ref))
         say(f"error-per-depth {alg} n={n} L=1/2/3 relF " + " / ".join(f"{e:.2e}" for e in errs))
         assert max(errs) <= 1e-12, (alg, errs)
+
+
+MIXED = [("fmm_424_26+strassen_222_7", ["fmm_424_26", "strassen_222_7"]),
+         ("strassen_222_7+fmm_323_15", ["strassen_222_7", "fmm_323_15"]),
+         ("fmm_333_23+fmm_423_20", ["fmm_333_23", "fmm_423_20"]),
+         ("strassen_222_7+fmm_424_26+strassen_222_7", ["strassen_222_7", "fmm_424_26", "strassen_222_7"])]
+
+
+@pytest.mark.parametrize("spec,names", MIXED)
+def test_mixed_levels_parity(F, spec, names):
+    """One base case per level (Section 5.2's composition): ragged sizes
+    against the binary64 oracle (FP64 gate), integer inputs bit-exact."""
+    algs = [algorithms.get(x) for x in names]
+    L = len(algs)
+    fm = int(np.prod([a.M for a in algs]))
+    fk = int(np.prod([a.K for a in algs]))
+    fn = int(np.prod([a.N for a in algs]))
+    m, k, n = fm * 3 + 1, fk * 2 + 1, fn * 3 + 2
+    say(f"case mixed {spec} m={m} k={k} n={n}")
+    A, B = fmm_inputs.operands(23, m, k, n, "uniform")
+    C = _run(F, spec, L, A, B, F.F64)
+    err = relf(C, classical.gemm(A, B))
+    say(f"  relF={err:.2e}")
+    assert err <= 1e-12
+    Ai, Bi = fmm_inputs.operands(23, m, k, n, "integer")
+    assert np.array_equal(_run(F, spec, L, Ai, Bi, F.F64), classical.gemm(Ai, Bi))
+
+
+@pytest.mark.parametrize("spec,names", MIXED[:2])
+def test_mixed_levels_stages_bit_exact(F, spec, names):
+    """Formation and combination of a mixed plan equal the oracle's per-level
+    chains bit for bit (leaf operands, and C from seeded leaf products)."""
+    algs = [algorithms.get(x) for x in names]
+    L = len(algs)
+    m = int(np.prod([a.M for a in algs])) * 3
+    k = int(np.prod([a.K for a in algs])) * 2
+    n = int(np.prod([a.N for a in algs])) * 3
+    say(f"case mixed stages {spec} m={m} k={k} n={n}")
+    A, B = fmm_inputs.operands(24, m, k, n, "uniform")
+    S = recursive.form_operands(algs, L, A, "A")
+    T = recursive.form_operands(algs, L, B, "B")
+    with F.Plan(spec, m, k, n, L, F.F64) as p:
+        info = p.info
+        dA, dB = to_dev(A), to_dev(B)
+        C = p.run_stage(F.STAGE_FORM_S, dA, dB)
+        p.run_stage(F.STAGE_FORM_T, dA, dB, C)
+        lm, lk, ln = info["leaf_m"], info["leaf_k"], info["leaf_n"]
+        for side, X, ref, (h, w) in ((0, A, S, (lm, lk)), (1, B, T, (lk, ln))):
+            for leaf in range(len(ref)):
+                loc, off, row, col, ld, alpha = p.operand(side, leaf)
+                if loc == F.LOC_WORKSPACE:
+                    got = ws_read(p, off, h, w, ld, np.float64) * alpha
+                else:
+                    got = X[row:row + h, col:col + w] * alpha
+                assert np.array_equal(got.view(np.int64), ref[leaf].view(np.int64)), (side, leaf)
+        Ms = []
+        for leaf in range(len(S)):
+            Mv = fmm_inputs.matrix(300 + leaf, 7, lm, ln, "uniform")
+            Ms.append(Mv)
+            loc, off, row, col, ld, alpha = p.operand(2, leaf)
+            ws_write(p, off, Mv, ld)
+        C = p.run_stage(F.STAGE_COMBINE, dA, dB)
+        got = to_host(C)
+    ref = recursive.combine_products(algs, L, Ms)
+    assert np.array_equal(got.view(np.int64), ref.view(np.int64))

@@ -292,6 +292,73 @@ def test_form_and_combine_reproduce_static_core(name):
     assert np.array_equal(C, recursive.fmm(a, L, A, B, peel="static"))
 
 
+# --- composition of different base cases across levels (Section 5.2) ---------
+
+MIXES = [("strassen_222_7", "fmm_424_26"), ("fmm_424_26", "strassen_222_7"),
+         ("fmm_323_15", "fmm_423_20"), ("fmm_333_23", "strassen_222_7")]
+
+
+@pytest.mark.parametrize("top,bottom", MIXES)
+def test_composed_base_case_passes_brent(top, bottom):
+    """Two levels of different base cases form one bilinear algorithm
+    <M1 M2, K1 K2, N1 N2; R1 R2>; its factor matrices pass the Brent
+    equations exactly, and swapping the order of the interleaved block
+    indices (a plausible slip) does not."""
+    a, b = algorithms.get(top), algorithms.get(bottom)
+    c = algorithms.compose(a, b)
+    assert (c.M, c.K, c.N, c.R) == (a.M * b.M, a.K * b.K, a.N * b.N, a.R * b.R)
+    assert tensor.brent_residual(c.U, c.V, c.W, c.M, c.K, c.N) == []
+    # the same composition with the level-one and level-two block indices of
+    # A's rows exchanged
+    bad = [list(r) for r in c.U]
+    rows, cols = c.M, c.K
+    perm = [(x % b.M) * a.M + x // b.M for x in range(rows)]
+    badU = tuple(tuple(bad[perm[i // cols] * cols + i % cols]) for i in range(rows * cols))
+    if perm != list(range(rows)):
+        assert tensor.brent_residual(badU, c.V, c.W, c.M, c.K, c.N) != []
+
+
+@pytest.mark.parametrize("top,bottom", MIXES[:3])
+@pytest.mark.parametrize("peel", ["dynamic", "static"])
+def test_recursive_mixed_levels_exact_on_rationals(top, bottom, peel):
+    """O2 with one base case per level equals the brute-force product exactly
+    on ragged sizes, and in binary64 agrees with one level of the composed
+    algorithm to rounding (the two sum the same terms in different orders)."""
+    a, b = algorithms.get(top), algorithms.get(bottom)
+    rng = random.Random(5)
+    fm, fk, fn = a.M * b.M, a.K * b.K, a.N * b.N
+    for (tm, tk, tn, rm, rk, rn) in [(1, 1, 1, 0, 0, 0), (1, 1, 1, 1, 1, 1), (2, 1, 1, fm - 1, 0, 1)]:
+        m, k, n = fm * tm + rm, fk * tk + rk, fn * tn + rn
+        if m * k * n > 40000:
+            continue
+        A = _frac_matrix(rng, m, k)
+        B = _frac_matrix(rng, k, n)
+        C = recursive.fmm([a, b], 2, A, B, peel=peel)
+        assert C.tolist() == classical.gemm_exact(A.tolist(), B.tolist()), (top, bottom, m, k, n)
+    rng2 = np.random.default_rng(4)
+    A = rng2.uniform(-1, 1, (fm * 2, fk * 2))
+    B = rng2.uniform(-1, 1, (fk * 2, fn * 3))
+    composed = recursive.fmm(algorithms.compose(a, b), 1, A, B, peel="static")
+    mixed = recursive.fmm([a, b], 2, A, B, peel="static")
+    assert np.linalg.norm(mixed - composed) <= 1e-13 * np.linalg.norm(composed)
+
+
+def test_form_and_combine_mixed_levels():
+    """The stage-by-stage chains with one base case per level reproduce the
+    mixed static-peel recursion bit for bit."""
+    a, b = algorithms.get("fmm_424_26"), algorithms.get("strassen_222_7")
+    rng = np.random.default_rng(10)
+    m, k, n = a.M * b.M * 3, a.K * b.K * 2, a.N * b.N * 3
+    A = rng.uniform(-1, 1, (m, k))
+    B = rng.uniform(-1, 1, (k, n))
+    S = recursive.form_operands([a, b], 2, A, "A")
+    T = recursive.form_operands([a, b], 2, B, "B")
+    assert len(S) == a.R * b.R
+    Ms = [classical.gemm(s, t) for s, t in zip(S, T)]
+    C = recursive.combine_products([a, b], 2, Ms)
+    assert np.array_equal(C, recursive.fmm([a, b], 2, A, B, peel="static"))
+
+
 # --- the BF16x3 emulation ----------------------------------------------------
 
 def test_bf16_round_to_nearest_even():

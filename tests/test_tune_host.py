@@ -151,7 +151,41 @@ def test_model_summary_equals_the_full_plan(fuse, dtype, monkeypatch):
                 assert c["workspace_bytes"] == i["workspace_bytes"], (shape, c)
                 assert abs(c["add_ms"] - i["add_bytes"] / 4.8e12 * 1e3) <= 1e-12 * max(1.0, c["add_ms"])
                 checked += 1
-    assert checked > 60
+        # one base case per level (two-level mixes from the model, and longer lists)
+        mixed = [c for c in F.rank_candidates(*shape, dtype, budget_bytes=1 << 50) if "+" in c["alg"]]
+        lists = [("fmm_333_23+strassen_222_7+fmm_424_26", 3), ("strassen_222_7+strassen_222_7+fmm_323_15", 3)]
+        for alg, L in [(c["alg"], c["levels"]) for c in mixed] + lists:
+            try:
+                p = F.Plan(alg, *shape, L, dtype=dtype, host_only=True)
+            except F.FmmError:
+                continue  # a leaf dimension < 1
+            c = F.rank_candidates(*shape, dtype, alg=alg, budget_bytes=1 << 50)[0]
+            i = p.info
+            assert (c["alg"], c["levels"]) == (alg, L)
+            assert c["workspace_bytes"] == i["workspace_bytes"], (shape, alg)
+            assert abs(c["add_ms"] - i["add_bytes"] / 4.8e12 * 1e3) <= 1e-12 * max(1.0, c["add_ms"])
+            assert i["fuse_levels"] == 1 and i["alg"] == alg
+            checked += 1
+    assert checked > 100
+
+
+def test_mixed_levels_planning():
+    """One base case per level: leaf dimensions are the size over the product
+    of the levels' block counts, R1 R2 leaves, one level per addition pass;
+    malformed lists are rejected."""
+    p = F.Plan("fmm_424_26+strassen_222_7", 16384, 16384, 16384, 2, host_only=True)
+    i = p.info
+    assert (i["leaf_m"], i["leaf_k"], i["leaf_n"]) == (2048, 4096, 2048)
+    assert i["num_leaves"] == 26 * 7 and i["fuse_levels"] == 1
+    assert i["alg"] == "fmm_424_26+strassen_222_7"
+    q = F.Plan("strassen_222_7+fmm_323_15", 1001, 900, 1100, 2, host_only=True).info
+    assert (q["m0"], q["k0"], q["n0"]) == (996, 900, 1098)
+    assert q["num_leaves"] == 7 * 15
+    for alg, L, code in [("fmm_424_26+strassen_222_7", 3, 1), ("fmm_424_26+nope", 2, 5),
+                         ("classical+strassen_222_7", 2, 5), ("fmm_424_26+", 2, 5)]:
+        with pytest.raises(F.FmmError) as e:
+            F.Plan(alg, 100, 100, 100, L, host_only=True)
+        assert e.value.code == code, (alg, L)
 
 
 def test_concurrent_planning_and_ranking_agree_with_serial():
