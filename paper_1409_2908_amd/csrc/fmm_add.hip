@@ -193,6 +193,87 @@ __global__ void __launch_bounds__(256) form2_kernel(FormArgs a) {
   }
 }
 
+// Split (BF16x3) leaf operands (one level, or two levels of a narrow base
+// case) with two positions per thread, so each store instruction writes two
+// bf16 of a plane (4 bytes per lane) instead of one.  S operands (row-major planes): positions (p, q) and
+// (p, q + 1), a wavefront covering 128 consecutive columns.  T operands
+// (k-octets): positions (p, q) and (p + 1, q) of one octet, a wavefront
+// covering 16 columns of one octet (256 contiguous bytes per plane).  Same
+// chains, in the same order, as form_kernel.
+template <int ID, int SIDE, int LV>
+__global__ void __launch_bounds__(256) form_split2_kernel(FormArgs a) {
+  using S = Side<ID, SIDE>;
+  constexpr int NB = S::NB, R = S::R, BR = S::BR, BC = S::BC;
+  constexpr int NIN = LV == 1 ? NB : NB * NB;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t p, q;
+  constexpr int dp = SIDE == 0 ? 0 : 1, dq = SIDE == 0 ? 1 : 0;
+  if constexpr (SIDE == 0) {
+    q = ((int64_t)blockIdx.x * 64 + lane) * 2;
+    p = (int64_t)blockIdx.y * 4 + wave;
+  } else {
+    q = (int64_t)blockIdx.x * 64 + wave * 16 + (lane >> 2);
+    p = (int64_t)blockIdx.y * 8 + 2 * (lane & 3);
+  }
+  if (q >= a.w || p >= a.h) return;
+  const bool two = q + dq < a.w && p + dp < a.h;
+  const int g = blockIdx.z;
+  const Ref src = a.groups[g];
+  int64_t ld;
+  const char* base = buf_ptr(a.bases, src, &ld);
+  const int64_t h = a.h, w = a.w;
+  double x0[NIN], x1[NIN];
+  static_for<0, NIN>([&](auto ic) {
+    constexpr int idx = decltype(ic)::value;
+    constexpr int i1 = LV == 1 ? idx : idx / NB;
+    constexpr int i2 = LV == 1 ? 0 : idx % NB;
+    constexpr int a1 = i1 / BC, b1 = i1 % BC, a2 = i2 / BC, b2 = i2 % BC;
+    const int64_t row = src.row + (LV == 1 ? a1 * h : (a1 * BR + a2) * h) + p;
+    const int64_t col = src.col + (LV == 1 ? b1 * w : (b1 * BC + b2) * w) + q;
+    const int64_t e = src.off + row * ld + col;
+    x0[idx] = load_elt(base, src.elt, e) * src.alpha;
+    x1[idx] = load_elt(base, src.elt, two ? e + dp * ld + dq : e) * src.alpha;
+  });
+  unsigned short* ws = (unsigned short*)a.bases.ptr[BUF_WS];
+  const int64_t* outs = a.outs + (int64_t)g * a.nout;
+  const int64_t pos = SIDE == 0 ? p * a.out_ld + q : (p >> 3) * a.out_ld + q * 8 + (p & 7);
+  auto put = [&](int64_t off, double v0, double v1) {
+    unsigned short h0, l0, h1, l1;
+    split_bits((float)v0, &h0, &l0);
+    split_bits((float)v1, &h1, &l1);
+    const int64_t i = off + pos;  // even: planes, rows and octets have even lengths
+    if (two) {
+      *(unsigned*)(ws + i) = (unsigned)h0 | ((unsigned)h1 << 16);
+      *(unsigned*)(ws + i + a.out_plane) = (unsigned)l0 | ((unsigned)l1 << 16);
+    } else {
+      ws[i] = h0;
+      ws[i + a.out_plane] = l0;
+    }
+  };
+  if constexpr (LV == 1) {
+    static_for<0, R>([&](auto rc) {
+      constexpr int r = decltype(rc)::value;
+      const int64_t off = outs[r];
+      if (off >= 0) put(off, chain_col<S, r, 1, NB>(x0), chain_col<S, r, 1, NB>(x1));
+    });
+  } else {
+    static_for<0, R>([&](auto r1c) {
+      constexpr int r1 = decltype(r1c)::value;
+      double y0[NB], y1[NB];
+      static_for<0, NB>([&](auto i2c) {
+        constexpr int i2 = decltype(i2c)::value;
+        y0[i2] = chain_col<S, r1, NB, NB>(x0 + i2);
+        y1[i2] = chain_col<S, r1, NB, NB>(x1 + i2);
+      });
+      static_for<0, R>([&](auto r2c) {
+        constexpr int r2 = decltype(r2c)::value;
+        const int64_t off = outs[r1 * R + r2];
+        if (off >= 0) put(off, chain_col<S, r2, 1, NB>(y0), chain_col<S, r2, 1, NB>(y1));
+      });
+    });
+  }
+}
+
 // W-combination, one level: C_k = sum_r W[k][r] M_r at each position.
 template <int ID>
 __global__ void __launch_bounds__(kAddTX * kAddTY) combine1_kernel(CombineArgs a) {
@@ -346,12 +427,25 @@ __global__ void __launch_bounds__(256) combine2_kernel(CombineArgs a) {
 template <int ID>
 static hipError_t launch_form_id(const FormArgs& a, int side, int lv, int ngroups, hipStream_t s) {
   dim3 block(kAddTX, kAddTY);
-  if (side == 1 && a.out_elt == ELT_BF16X2) {
-    dim3 grid((unsigned)((a.w + 31) / 32), (unsigned)((a.h + 7) / 8), (unsigned)ngroups);
-    if (lv == 1) hipLaunchKernelGGL((form_kernel<ID, 1, 1, true>), grid, block, 0, s, a);
-    else if (lv == 2) hipLaunchKernelGGL((form_kernel<ID, 1, 2, true>), grid, block, 0, s, a);
-    else return hipErrorInvalidValue;
+  if (a.out_elt == ELT_BF16X2 && (lv == 1 || (lv == 2 && Alg<ID>::R <= 8))) {
+    const dim3 g2 = side == 0 ? dim3((unsigned)((a.w + 127) / 128), (unsigned)((a.h + 3) / 4), (unsigned)ngroups)
+                              : dim3((unsigned)((a.w + 63) / 64), (unsigned)((a.h + 7) / 8), (unsigned)ngroups);
+    if (side == 0 && lv == 1) hipLaunchKernelGGL((form_split2_kernel<ID, 0, 1>), g2, dim3(256), 0, s, a);
+    else if (side == 1 && lv == 1) hipLaunchKernelGGL((form_split2_kernel<ID, 1, 1>), g2, dim3(256), 0, s, a);
+    else if constexpr (Alg<ID>::R <= 8) {
+      if (side == 0) hipLaunchKernelGGL((form_split2_kernel<ID, 0, 2>), g2, dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((form_split2_kernel<ID, 1, 2>), g2, dim3(256), 0, s, a);
+    }
     return hipGetLastError();
+  }
+  if constexpr (Alg<ID>::R > 8) {
+    // split T operands of two fused levels of a wide base case: the register
+    // kernel with the 8 x 8 wavefront mapping of the k-octet layout
+    if (side == 1 && a.out_elt == ELT_BF16X2 && lv == 2) {
+      dim3 grid((unsigned)((a.w + 31) / 32), (unsigned)((a.h + 7) / 8), (unsigned)ngroups);
+      hipLaunchKernelGGL((form_kernel<ID, 1, 2, true>), grid, block, 0, s, a);
+      return hipGetLastError();
+    }
   }
   // Two fused levels of a wide base case go through LDS, except split T
   // operands (k-octet layout), which keep the register kernel's 8 x 8 mapping.
