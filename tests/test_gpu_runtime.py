@@ -38,7 +38,9 @@ def _check_oracle(F, alg, L, A, B, C, dtype):
     elif dtype == F.F32:
         assert relf(C, ref) <= 2e-6 * 2 ** L
     else:
-        emu = bf16x3.gemm(A, B) if alg == "classical" else bf16x3.fmm(algorithms.get(alg), L, A, B)
+        levels = [algorithms.get(x) for x in alg.split("+")] if "+" in alg else None
+        emu = (bf16x3.gemm(A, B) if alg == "classical"
+               else bf16x3.fmm(levels if levels else algorithms.get(alg), L, A, B))
         assert relf(C, emu) <= 2e-6 * 2 ** max(L, 1)
 
 
@@ -196,3 +198,37 @@ def test_server_continuous_batching(F):
         _check_oracle(F, c["alg"], c["levels"], A, B, got, dt)
     assert max(sizes) > 1  # requests were batched
     torch.cuda.synchronize()
+
+
+MIXED_BATCH = [("fmm_424_26+strassen_222_7", 2, (300, 130, 270), 0), ("strassen_222_7+fmm_323_15", 2, (250, 90, 260), 0),
+               ("fmm_424_26+strassen_222_7", 2, (300, 130, 270), 2), ("strassen_222_7", 2, (200, 200, 200), 0),
+               ("fmm_333_23+strassen_222_7", 2, (190, 140, 200), 1)]
+
+
+def test_batched_mixed_levels_and_graph(F):
+    """Plans with one base case per level in a batch with other plans, and
+    replayed from a recorded graph: bitwise those of each plan alone."""
+    import torch
+    plans, As, Bs, host = [], [], [], []
+    for i, (alg, L, (m, k, n), dt) in enumerate(MIXED_BATCH):
+        A, B = fmm_inputs.operands(60 + i, m, k, n, "uniform", _np_dtype(F, dt))
+        plans.append(F.Plan(alg, m, k, n, L, dt))
+        As.append(to_dev(A))
+        Bs.append(to_dev(B))
+        host.append((A, B))
+    say("case batched mixed-level plans")
+    Cs = F.multiply_batched(plans, As, Bs)
+    torch.cuda.synchronize()
+    for (alg, L, shape, dt), (A, B), C in zip(MIXED_BATCH, host, Cs):
+        got = to_host(C)
+        assert np.array_equal(got, _alone(F, alg, L, A, B, dt)), (alg, shape, dt)
+        _check_oracle(F, alg, L, A, B, got, dt)
+    for p in plans:
+        p.close()
+    alg, L, (m, k, n), dt = MIXED_BATCH[0]
+    A, B = host[0]
+    with F.Plan(alg, m, k, n, L, dt, use_graph=True) as p:
+        dA, dB = to_dev(A), to_dev(B)
+        outs = [to_host(p.multiply(dA, dB)) for _ in range(3)]
+    for o in outs:
+        assert np.array_equal(o, _alone(F, alg, L, A, B, dt))
