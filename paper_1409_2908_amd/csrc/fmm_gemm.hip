@@ -9,9 +9,7 @@
 // beyond one tile.
 //
 // Tile: 128 x 128 per workgroup of 4 wavefronts (2 x 2), 64 x 64 per
-// wavefront = 4 x 4 MFMA 16x16x4 blocks (a 64 x 64 variant, 32 x 32 per
-// wavefront, serves launches with too few large tiles to fill the chip; the
-// launcher picks the shape and re-counts the tiles).  Two workgroups share each compute
+// wavefront = 4 x 4 MFMA 16x16x4 blocks.  Two workgroups share each compute
 // unit (so each SIMD runs two wavefronts of different workgroups, whose
 // barriers do not line up and keep the matrix pipe fed).  K advances 16 at a
 // time through a double-buffered LDS stage: global loads for step k+1 are

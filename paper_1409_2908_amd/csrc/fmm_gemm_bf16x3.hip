@@ -15,8 +15,7 @@
 // Work decomposition and scheduling follow the FP64/FP32 kernel: one flat tile
 // space over all problems, ~2 workgroups of 4 wavefronts per CU, 128 x 128
 // tiles, 64 x 64 per wavefront = 4 x 4 blocks of v_mfma_f32_16x16x32_bf16, XCD
-// aware tile order (and 64 x 64 tiles for launches with fewer 128 x 128 tiles
-// than compute units).  K advances 32 per step through double-buffered LDS that
+// aware tile order.  K advances 32 per step through double-buffered LDS that
 // holds the hi and lo planes of A (row-major, k contiguous) and of B
 // transposed (n-major, k contiguous), so each lane's MFMA fragment (8
 // consecutive k of one row / column) is one 16-byte LDS read.  Operands are
