@@ -3,8 +3,9 @@ one by one.
 
 Shapes: the FP64 rectangular workloads (16384 x 1600 x 16384,
 16384 x 16384 x 2400, 9000^3, the last with and without peeling), the FP64
-square 16384^3 and the FP32 16384^3 BF16x3 workload, each with the base case
-and depth the benchmark runs there.  Every sampled set holds the first and
+square 16384^3 (also at three levels) and the FP32 BF16x3 workloads (16384^3
+at two levels, 8192^3 at three), each with the base case the benchmark runs
+there.  Every sampled set holds the first and
 last row, every leaf-block boundary row and every row of the m-peel strip;
 each sampled row holds all n columns, so the n-peel strip is checked in
 every row.
@@ -62,8 +63,9 @@ def _sampled(F, alg, L, A, B, dtype, rows):
 @pytest.mark.parametrize("m,k,n,alg,L", [(16384, 1600, 16384, "fmm_424_26", 2),
                                          (16384, 16384, 2400, "strassen_222_7", 2),
                                          (9000, 9000, 9000, "fmm_323_15", 2),
-                                         (9000, 9000, 9000, "fmm_424_26", 2)])
-def test_fp64_rectangular_full_size(F, m, k, n, alg, L):
+                                         (9000, 9000, 9000, "fmm_424_26", 2),
+                                         (16384, 16384, 16384, "strassen_222_7", 3)])
+def test_fp64_full_size(F, m, k, n, alg, L):
     say(f"case fullsize fp64 {alg} L={L} {m}x{k}x{n}")
     A, B = fmm_inputs.operands(21, m, k, n, "uniform")
     rows = _rows(alg, L, m, 16, 21)
@@ -86,8 +88,9 @@ def test_integer_full_size_bit_exact(F, dtype_name, alg, L):
     assert np.array_equal(got, ref)
 
 
-def test_bf16x3_rowscaled_full_size(F):
-    n, alg, L = 16384, "strassen_222_7", 2
+@pytest.mark.parametrize("n,L", [(16384, 2), (8192, 3)])
+def test_bf16x3_rowscaled_full_size(F, n, L):
+    alg = "strassen_222_7"
     say(f"case fullsize bf16x3 rowscaled {alg} L={L} n={n}")
     A, B = fmm_inputs.operands(23, n, n, n, "normal_rowscaled", np.float32)
     rows = _rows(alg, L, n, 16, 23)
