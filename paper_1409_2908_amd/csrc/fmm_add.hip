@@ -44,16 +44,16 @@ __device__ __forceinline__ void store_out(char* ws, int elt, int64_t idx, int64_
 // then covers 8 consecutive rows p of 8 consecutive columns q, so every
 // 2-byte store instruction of the wavefront fills 128 contiguous bytes (8
 // whole octets) instead of scattering over 1 KB.
-template <int ID, int SIDE, int LV, bool OCT = false>
-__global__ void __launch_bounds__(kAddTX * kAddTY) form_kernel(FormArgs a) {
+template <int ID, int SIDE, int LV, bool OCT>
+__device__ __forceinline__ void form_body(const FormArgs& a, unsigned bx, unsigned by, unsigned bz) {
   using S = Side<ID, SIDE>;
   constexpr int NB = S::NB, R = S::R, BR = S::BR, BC = S::BC;
   constexpr int NIN = LV == 1 ? NB : NB * NB;
   const int t = threadIdx.y * kAddTX + threadIdx.x;
-  const int64_t q = OCT ? (int64_t)blockIdx.x * 32 + (t >> 3) : (int64_t)blockIdx.x * kAddTX + threadIdx.x;
-  const int64_t p = OCT ? (int64_t)blockIdx.y * 8 + (t & 7) : (int64_t)blockIdx.y * kAddTY + threadIdx.y;
+  const int64_t q = OCT ? (int64_t)bx * 32 + (t >> 3) : (int64_t)bx * kAddTX + threadIdx.x;
+  const int64_t p = OCT ? (int64_t)by * 8 + (t & 7) : (int64_t)by * kAddTY + threadIdx.y;
   if (q >= a.w || p >= a.h) return;
-  const int g = blockIdx.z;
+  const int g = (int)bz;
   const Ref src = a.groups[g];
   int64_t ld;
   const char* base = buf_ptr(a.bases, src, &ld);
@@ -94,6 +94,27 @@ __global__ void __launch_bounds__(kAddTX * kAddTY) form_kernel(FormArgs a) {
         if (off >= 0) store_out(ws, a.out_elt, off + pos, a.out_plane, chain_col<S, r2, 1, NB>(y));
       });
     });
+  }
+}
+
+template <int ID, int SIDE, int LV, bool OCT = false>
+__global__ void __launch_bounds__(kAddTX * kAddTY) form_kernel(FormArgs a) {
+  form_body<ID, SIDE, LV, OCT>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// One level of S and of T in a single launch, for small problems where the
+// idle time between dependent launches is comparable to a pass: blocks
+// [0, xs) of the x dimension form S on an xs x ys x zs grid, the rest form T
+// on its own yt x zt extent; blocks outside a side's grid do nothing.  The
+// body (and so every stored value) is the one form_kernel runs.
+template <int ID>
+__global__ void __launch_bounds__(kAddTX * kAddTY) form_pair_kernel(FormArgs s, FormArgs t, unsigned xs,
+                                                                    unsigned ys, unsigned zs, unsigned yt,
+                                                                    unsigned zt) {
+  if (blockIdx.x < xs) {
+    if (blockIdx.y < ys && blockIdx.z < zs) form_body<ID, 0, 1, false>(s, blockIdx.x, blockIdx.y, blockIdx.z);
+  } else if (blockIdx.y < yt && blockIdx.z < zt) {
+    form_body<ID, 1, 1, false>(t, blockIdx.x - xs, blockIdx.y, blockIdx.z);
   }
 }
 
@@ -467,6 +488,32 @@ static hipError_t launch_form_id(const FormArgs& a, int side, int lv, int ngroup
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int ID>
+static hipError_t launch_form_pair_id(const FormArgs& sa, int ngs, const FormArgs& ta, int ngt, hipStream_t st) {
+  const unsigned xs = (unsigned)((sa.w + kAddTX - 1) / kAddTX), ys = (unsigned)((sa.h + kAddTY - 1) / kAddTY);
+  const unsigned xt = (unsigned)((ta.w + kAddTX - 1) / kAddTX), yt = (unsigned)((ta.h + kAddTY - 1) / kAddTY);
+  const dim3 grid(xs + xt, ys > yt ? ys : yt, (unsigned)(ngs > ngt ? ngs : ngt));
+  hipLaunchKernelGGL((form_pair_kernel<ID>), grid, dim3(kAddTX, kAddTY), 0, st, sa, ta, xs, ys, (unsigned)ngs, yt,
+                     (unsigned)ngt);
+  return hipGetLastError();
+}
+
+hipError_t launch_form_pair(int alg, const FormArgs& sa, int ngs, const FormArgs& ta, int ngt, hipStream_t st) {
+  // one-level passes with unsplit outputs and non-empty grids on both sides
+  if (sa.out_elt == ELT_BF16X2 || ta.out_elt == ELT_BF16X2 || sa.h <= 0 || sa.w <= 0 || ta.h <= 0 || ta.w <= 0 ||
+      ngs <= 0 || ngt <= 0)
+    return hipErrorInvalidValue;
+  switch (alg) {
+    case 0: return launch_form_pair_id<0>(sa, ngs, ta, ngt, st);
+    case 1: return launch_form_pair_id<1>(sa, ngs, ta, ngt, st);
+    case 2: return launch_form_pair_id<2>(sa, ngs, ta, ngt, st);
+    case 3: return launch_form_pair_id<3>(sa, ngs, ta, ngt, st);
+    case 4: return launch_form_pair_id<4>(sa, ngs, ta, ngt, st);
+    case 5: return launch_form_pair_id<5>(sa, ngs, ta, ngt, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_form(int alg, const FormArgs& a, int side, int lv, int ngroups, hipStream_t s) {

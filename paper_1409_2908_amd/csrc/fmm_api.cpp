@@ -153,6 +153,25 @@ hipError_t run_form(const fmm::Plan& P, const std::vector<fmm::FormPass>& passes
   return hipSuccess;
 }
 
+// Both one-level passes of a pair_form plan in one launch (T is formed by
+// the S stage; the T stage then has nothing to do).
+hipError_t run_form_pair(const fmm::Plan& P, const fmm::Bases& b, hipStream_t s) {
+  fmm::FormArgs a[2];
+  const fmm::FormPass* fp[2] = {&P.s_passes[0], &P.t_passes[0]};
+  for (int i = 0; i < 2; ++i) {
+    a[i].bases = b;
+    a[i].groups = table_ptr<fmm::Ref>(P, fp[i]->dev_groups);
+    a[i].outs = table_ptr<int64_t>(P, fp[i]->dev_outs);
+    a[i].h = fp[i]->h;
+    a[i].w = fp[i]->w;
+    a[i].out_ld = fp[i]->out_ld;
+    a[i].out_plane = fp[i]->out_plane;
+    a[i].out_elt = fp[i]->out_elt;
+    a[i].nout = fp[i]->nout;
+  }
+  return fmm::launch_form_pair(fp[0]->alg, a[0], fp[0]->ngroups, a[1], fp[1]->ngroups, s);
+}
+
 // Appends plan P's GEMM groups to a (possibly shared) grouped launch, with
 // P's operand bases in slot `slot`.
 void append_leaf(fmm::GemmArgs& a, const fmm::Plan& P, const fmm::Bases& b, int slot) {
@@ -202,8 +221,8 @@ hipError_t run_combine(const fmm::Plan& P, const fmm::Bases& b, hipStream_t s) {
 
 hipError_t run_stage(const fmm::Plan& P, int stage, const fmm::Bases& b, hipStream_t s) {
   switch (stage) {
-    case FMM_STAGE_FORM_S: return run_form(P, P.s_passes, b, s);
-    case FMM_STAGE_FORM_T: return run_form(P, P.t_passes, b, s);
+    case FMM_STAGE_FORM_S: return P.pair_form ? run_form_pair(P, b, s) : run_form(P, P.s_passes, b, s);
+    case FMM_STAGE_FORM_T: return P.pair_form ? hipSuccess : run_form(P, P.t_passes, b, s);
     case FMM_STAGE_LEAF: return run_leaf(P, b, s);
     case FMM_STAGE_COMBINE: return run_combine(P, b, s);
   }
@@ -311,6 +330,16 @@ fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
   }
   fmm::Plan& P = h->P;
   P.leaf_tile = leaf_tile;
+  // Small one-level plans form S and T in one launch: between two dependent
+  // launches the queue idles about as long as one such pass takes.
+  if (P.s_passes.size() == 1 && P.t_passes.size() == 1) {
+    const fmm::FormPass& fs = P.s_passes[0];
+    const fmm::FormPass& ft = P.t_passes[0];
+    P.pair_form = fs.lv == 1 && ft.lv == 1 && fs.alg == ft.alg && fs.out_elt != fmm::ELT_BF16X2 &&
+                  ft.out_elt != fmm::ELT_BF16X2 && fs.h > 0 && fs.w > 0 && ft.h > 0 && ft.w > 0 &&
+                  fs.ngroups > 0 && ft.ngroups > 0 &&
+                  fs.h * fs.w * fs.ngroups + ft.h * ft.w * ft.ngroups <= (int64_t(1) << 20);
+  }
   if (device) {
     if (const char* bud = std::getenv("FMM_HBM_BUDGET")) {
       const double budget = std::atof(bud);

@@ -182,6 +182,7 @@ struct Plan {
   int64_t timed = 0;            // timed multiplies since timing was enabled
   bool external = false;        // device memory bound by the caller (not owned)
   bool use_graph = false;       // replay the stages as a captured HIP graph
+  bool pair_form = false;       // S and T formed by one launch (small one-level plans)
   int leaf_tile = 0;            // FP64 / FP32 leaf tile edge: 64, 128, or 0 (chosen per launch)
   void* graph_exec = nullptr;   // hipGraphExec_t of the last capture
   void* cap_stream = nullptr;   // private stream the capture is recorded on

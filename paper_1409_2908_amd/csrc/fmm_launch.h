@@ -11,6 +11,8 @@ namespace fmm {
 constexpr bool kHaveBf16x3 = true;
 
 hipError_t launch_form(int alg, const FormArgs& a, int side, int lv, int ngroups, hipStream_t s);
+// One-level S and T passes (unsplit outputs) in one launch; the same values as two launch_form calls.
+hipError_t launch_form_pair(int alg, const FormArgs& sa, int ngs, const FormArgs& ta, int ngt, hipStream_t st);
 hipError_t launch_combine(int alg, const CombineArgs& a, int lv, int ngroups, hipStream_t s);
 // Grouped GEMM over every problem in `a`; the element type (a.elt) and the
 // dtype (0: FP64 MFMA, 1: FP32 MFMA, 2: BF16x3 MFMA) select the kernel.
