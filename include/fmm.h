@@ -159,6 +159,30 @@ fmm_status fmm_plan_bind(fmm_plan_t p, void *mem, size_t bytes, void *stream);
 fmm_status fmm_multiply(fmm_plan_t p, const void *A, int64_t lda, const void *B, int64_t ldb,
                         void *C, int64_t ldc, void *stream);
 
+/* Capacity of fmm_multiply_noalloc's device array, in bytes (64 MiB). */
+#define FMM_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * enqueue C = A*B with plan p exactly as fmm_multiply does (same kernels, same
+ * arithmetic, bitwise the same result), but with the plan's workspace and
+ * descriptor tables placed in a fixed device array that the library holds on
+ * each GPU from load until the process ends, instead of in the plan's own or
+ * bound memory.  Make p with fmm_plan_ex and defer_device_memory (then the
+ * plan holds no device memory at all); a plan that owns memory is accepted
+ * and its memory is left untouched.  The call allocates nothing: it enqueues
+ * the upload of the plan's descriptor tables (a host-to-device copy) and the
+ * stage kernels on `stream`.  Limit: fmm_plan_device_bytes(p) must be at most
+ * FMM_NOALLOC_MAX_BYTES, else FMM_ENOMEM and nothing is enqueued.  The array
+ * is shared by every call on one GPU and keeps the last call's contents
+ * (nothing in it needs to start at zero): calls that overlap on one GPU (on
+ * different streams, or from several threads without ordering) race and give
+ * wrong results; calls ordered on one stream are safe.  Other arguments and
+ * errors as fmm_multiply.  Use graph replay or stage timing through
+ * fmm_multiply; this call runs the stages directly and records no events. */
+fmm_status fmm_multiply_noalloc(fmm_plan_t p, const void *A, int64_t lda, const void *B, int64_t ldb,
+                                void *C, int64_t ldc, void *stream);
+
 /* Enqueue count products C[i] = A[i] * B[i], each with its own plan
  * plans[i] (all on the current device, each plan at most once), as one batch:
  * the S and T formations of every request, then grouped leaf launches that

@@ -21,6 +21,7 @@ __all__ = ["FmmError", "Plan", "Server", "gemm", "multiply_batched", "rank_candi
 F64, F32, F32_BF16X3 = 0, 1, 2
 STAGE_FORM_S, STAGE_FORM_T, STAGE_LEAF, STAGE_COMBINE = 0, 1, 2, 3
 LOC_A, LOC_B, LOC_C, LOC_WORKSPACE = 0, 1, 2, 3
+NOALLOC_MAX_BYTES = 64 << 20  # FMM_NOALLOC_MAX_BYTES of fmm.h
 _DTYPE_NAMES = {"f64": F64, "float64": F64, "f32": F32, "float32": F32, "bf16x3": F32_BF16X3,
                 "f32_bf16x3": F32_BF16X3}
 
@@ -103,6 +104,7 @@ def _load():
         "fmm_plan_ex": ([ctypes.POINTER(P), ctypes.c_char_p, i64, i64, i64, i32, i32,
                          ctypes.POINTER(_Options)], i32),
         "fmm_multiply": ([P, vp, i64, vp, i64, vp, i64, vp], i32),
+        "fmm_multiply_noalloc": ([P, vp, i64, vp, i64, vp, i64, vp], i32),
         "fmm_multiply_batched": ([ctypes.POINTER(P), ctypes.POINTER(vp), ctypes.POINTER(i64),
                                   ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(vp),
                                   ctypes.POINTER(i64), i32, vp], i32),
@@ -239,6 +241,16 @@ class Plan:
     def multiply(self, A, B, C=None, stream=None):
         a, lda, b, ldb, c, ldc, C = self._args(A, B, C)
         _check(_lib.fmm_multiply(self._p, a, lda, b, ldb, c, ldc, _stream_ptr(stream)))
+        return C
+
+    def multiply_noalloc(self, A, B, C, stream=None):
+        """C = A @ B through fmm_multiply_noalloc: the workspace and tables go
+        into the library's fixed device array (at most NOALLOC_MAX_BYTES), so
+        nothing is allocated; C must be given."""
+        if C is None:
+            raise ValueError("multiply_noalloc needs the output tensor C")
+        a, lda, b, ldb, c, ldc, C = self._args(A, B, C)
+        _check(_lib.fmm_multiply_noalloc(self._p, a, lda, b, ldb, c, ldc, _stream_ptr(stream)))
         return C
 
     def run_stage(self, stage, A, B, C=None, stream=None):

@@ -293,6 +293,32 @@ fmm_status capture_graph(fmm::Plan& P, const fmm::Bases& b) {
   return FMM_OK;
 }
 
+// Device memory of fmm_multiply_noalloc: a fixed array that every GPU the
+// library runs on holds from module load until the process ends.  In host
+// code the name `scratch` only stands in for the device symbol; the array's
+// device address on each GPU comes from hipGetSymbolAddress (scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[FMM_NOALLOC_MAX_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device, NULL until looked up
+
+// Address of `scratch` on device `dev`, which must be the current device:
+// looked up once per device (each GPU holds its own copy at its own address).
+fmm_status scratch_ptr(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(FMM_EUNSUPPORTED, "device index beyond the library's table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the no-allocation scratch array");
+    if (!p) return fail(FMM_EHIP, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return FMM_OK;
+}
+
 fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
                        int dtype, int fuse, bool device, bool defer = false, bool graph = false,
                        int leaf_tile = 0) {
@@ -498,6 +524,41 @@ fmm_status fmm_multiply(fmm_plan_t p, const void* A, int64_t lda, const void* B,
     ++P.timed;
   }
   return FMM_OK;
+}
+
+fmm_status fmm_multiply_noalloc(fmm_plan_t p, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                                int64_t ldc, void* stream) {
+  if (!p) return fail(FMM_EINVAL, "plan is NULL");
+  fmm::Plan& P = p->P;
+  if (P.host_only) return fail(FMM_EINVAL, "host-only plan cannot run");
+  fmm_status st = validate(P, A, lda, B, ldb, C, ldc);
+  if (st != FMM_OK) return st;
+  if (P.m == 0 || P.n == 0) return FMM_OK;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != P.device) return fail(FMM_EINVAL, "plan belongs to another device");
+  const size_t need = table_offset(P) + P.table_bytes;
+  if (need > (size_t)FMM_NOALLOC_MAX_BYTES)
+    return fail(FMM_ENOMEM, "plan needs " + std::to_string(need) + " device bytes (workspace + tables); " +
+                                "fmm_multiply_noalloc has " + std::to_string((size_t)FMM_NOALLOC_MAX_BYTES));
+  void* mem = nullptr;
+  st = scratch_ptr(cur, &mem);
+  if (st != FMM_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // The plan's device pointers name the array for this call only; every
+  // launch below takes them as kernel arguments, so the plan's own memory (or
+  // its binding) is left as it was.
+  void* const ws0 = P.ws;
+  void* const tab0 = P.dev_table;
+  P.ws = P.ws_bytes ? mem : nullptr;
+  P.dev_table = (char*)mem + table_offset(P);
+  e = hipMemcpyAsync(P.dev_table, P.table.data(), P.table_bytes, hipMemcpyHostToDevice, s);
+  const fmm::Bases b = make_bases(P, A, lda, B, ldb, C, ldc);
+  for (int stage = 0; stage < FMM_NUM_STAGES && e == hipSuccess; ++stage) e = run_stage(P, stage, b, s);
+  P.ws = ws0;
+  P.dev_table = tab0;
+  return e == hipSuccess ? FMM_OK : hip_fail(e, "no-allocation multiply");
 }
 
 fmm_status fmm_multiply_batched(const fmm_plan_t* plans, const void* const* A, const int64_t* lda,
