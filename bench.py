@@ -163,6 +163,24 @@ def main():
         plain_fp32 = round(classical_rate(F.F32)[1], 3)
         log(f"[bench] plain FP32 classical MFMA GEMM: {plain_fp32} TFLOP/s")
 
+    # the vendor BLAS on the same GPU (torch.matmul: rocBLAS / hipBLASLt),
+    # called only, in the operands' own precision
+    def vendor_rate():
+        for _ in range(2):
+            torch.matmul(dA, dB, out=dC)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        vsteps = max(3, min(args.steps, 5))
+        ev0.record(stream)
+        for _ in range(vsteps):
+            torch.matmul(dA, dB, out=dC)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return 2.0 * m * k * n / (ev0.elapsed_time(ev1) / vsteps * 1e-3) / 1e12
+
+    vendor_tflops = vendor_rate()
+    log(f"[bench] vendor GEMM (torch.matmul, {'FP64' if dt == F.F64 else 'FP32'}): {vendor_tflops:.2f} TFLOP/s")
+
     # error on sampled rows + CPU baseline (the oracle on those rows)
     plan.multiply(dA, dB, dC)
     torch.cuda.synchronize()
@@ -223,7 +241,9 @@ def main():
                    "fuse_levels": info["fuse_levels"]},
         "classical_same_gpu_tflops": round(classical_tflops, 3),
         "classical_plain_fp32_tflops": plain_fp32,
+        "vendor_gemm_tflops": round(vendor_tflops, 3),
         "speedup_vs_classical": round(eff_tflops / classical_tflops, 4),
+        "speedup_vs_vendor": round(eff_tflops / vendor_tflops, 4),
         "error_relF_sampled_rows": err,
         "stage_ms": {"form_s": stage_ms[0], "form_t": stage_ms[1], "leaf_gemm": stage_ms[2],
                      "combine": stage_ms[3]},
@@ -236,6 +256,41 @@ def main():
     plan.close()
 
 
+def oracle_check_kept(F, kept, rows_per_request=8, seed=500):
+    """The kept served requests against the CPU oracle on sampled rows (first,
+    last and seeded rows of each product): FP64 within 1e-12, BF16x3 within
+    its error gate (oracle.bf16x3.gate for the request's plan).  Returns the
+    largest error and the largest error / gate per dtype; raises if one is
+    above its gate."""
+    import torch
+    import fmm_inputs
+    from oracle import algorithms, bf16x3, classical
+    worst = {}
+    for idx, r in sorted(kept.items()):
+        c = r["completion"]
+        m, k = r["A"].shape
+        rows = fmm_inputs.sample_rows(seed + idx, m, rows_per_request, [0, m - 1])
+        ri = torch.from_numpy(rows).to(r["A"].device)
+        Ar = r["A"][ri].double().cpu().numpy()
+        got = r["C"][ri].double().cpu().numpy()
+        ref = classical.gemm_rows(Ar, r["B"].double().cpu().numpy(), np.arange(len(rows)))
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        if r["dtype"] == F.F64:
+            tol, name = 1e-12, "f64"
+        else:
+            names = c["alg"].split("+")
+            algs = None if c["levels"] == 0 or c["alg"] == "classical" else (
+                [algorithms.get(x) for x in names] if len(names) > 1 else algorithms.get(names[0]))
+            tol, name = bf16x3.gate(algs, c["levels"], k), "bf16x3"
+        if err > tol:
+            raise AssertionError(f"request {idx} ({c['alg']} L={c['levels']}): relF {err:.3e} above {tol:.3e}")
+        w = worst.setdefault(name, {"max_relF": 0.0, "max_relF_over_gate": 0.0, "checked": 0})
+        w["max_relF"] = max(w["max_relF"], err)
+        w["max_relF_over_gate"] = max(w["max_relF_over_gate"], err / tol)
+        w["checked"] += 1
+    return worst
+
+
 def run_serving(args):
     """Config: a Poisson stream of FP64 / FP32 (BF16x3) requests, each of m, k, n
     log-uniform on [256, 8192].  Capacity is measured first with every request
@@ -244,6 +299,7 @@ def run_serving(args):
     batching) for comparison.  A seeded subset of the served requests is
     recomputed alone and must match the result from the mix bit for bit."""
     import torch
+    import paper_1409_2908_amd as F
     from paper_1409_2908_amd import serving
 
     reqs = serving.make_requests(7, args.requests)
@@ -267,6 +323,8 @@ def run_serving(args):
     log(f"[serving] Poisson at {rate:.1f} req/s, one-at-a-time classical: {cl}")
     checked = serving.check_alone(kept)
     log(f"[serving] {checked} requests recomputed alone: bitwise equal")
+    oracle_errors = oracle_check_kept(F, kept)
+    log(f"[serving] {checked} requests against the CPU oracle on sampled rows: {oracle_errors}")
     cap_graph, _ = serving.run_stream(reqs, zeros, pools, use_graph=True, **common)
     log(f"[serving] capacity, fast path, one HIP graph per batch: {cap_graph}")
     fast_graph, kept_g = serving.run_stream(reqs, arr, pools, keep=keep, use_graph=True, **common)
@@ -285,6 +343,7 @@ def run_serving(args):
         "capacity_fast": cap_fast, "capacity_classical": cap_cl,
         "fast_graph": fast_graph, "capacity_fast_graph": cap_graph,
         "alone_vs_mix_checked": checked, "alone_vs_mix_checked_graph": checked_g,
+        "oracle_sampled_rows": oracle_errors,
     }
     print(json.dumps(out), flush=True)
 

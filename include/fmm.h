@@ -55,8 +55,9 @@ typedef enum {
 
 /* Stages of one multiply, in execution order (for fmm_run_stage and timing). */
 typedef enum {
-    FMM_STAGE_FORM_S = 0,  /* S operands from A (Section 3.1, first bullet; 3.2 streaming) */
-    FMM_STAGE_FORM_T = 1,  /* T operands from B */
+    FMM_STAGE_FORM_S = 0,  /* S operands from A (Section 3.1, first bullet; 3.2 streaming);
+                              for pair_form plans (fmm_plan_info_t) also the T operands */
+    FMM_STAGE_FORM_T = 1,  /* T operands from B (nothing for pair_form plans) */
     FMM_STAGE_LEAF = 2,    /* grouped leaf GEMMs M_rho = alpha S_rho T_rho, plus peel strips */
     FMM_STAGE_COMBINE = 3, /* C blocks from the M_rho by W (Section 3.1, third bullet) */
     FMM_NUM_STAGES = 4
@@ -86,6 +87,19 @@ typedef struct {
     char alg[80];                /* base case planned ("classical" for a plain GEMM), or one
                                     per level joined by '+'; for "auto" the model's choice */
     int leaf_tile;               /* leaf tile edge asked for (64 / 128), 0: chosen per launch */
+    int pair_form;               /* non-zero: S and T are formed by one launch, in the
+                                    FMM_STAGE_FORM_S stage (one-level plans of at most 2^20
+                                    formation positions, FP64 / FP32); FMM_STAGE_FORM_T then
+                                    enqueues nothing */
+    double error_bound;          /* predicted bound on the relative Frobenius error of C
+                                    against the exact product: e0 * prod over the levels of the
+                                    base case's error growth g, e0 = c + (2 + sqrt(k)) u, u the
+                                    leaf arithmetic's unit roundoff (2^-53 FP64, 2^-24 FP32),
+                                    c = 3 * 2^-16 on the BF16x3 path (split residuals and the
+                                    dropped lo*lo term), else 0;
+                                    g = sqrt(sum_r |u_r|^2 |v_r|^2 |w_r|^2 / (M K N)) over the
+                                    columns of U, V, W (the root-mean-square error growth of one
+                                    step for i.i.d. zero-mean operands: 1 classical, 2 Strassen) */
 } fmm_plan_info_t;
 
 /* Options of fmm_plan_ex.  Zero-initialise, then set what you need. */
@@ -104,6 +118,10 @@ typedef struct {
                           chosen per launch, 64 when the launch has fewer 128 x 128 tiles than
                           the device has compute units.  BF16x3 leaves always use 128.  Other
                           values: FMM_EINVAL.  Batched launches always choose per launch. */
+    double max_error;  /* automatic choice only (alg "auto" or levels -1): the largest
+                          error_bound (fmm_plan_info_t) a chosen plan may have; 0: the dtype's
+                          default (1e-12 FP64, 1e-4 FP32, 5e-4 BF16x3); < 0: no limit.
+                          Plans named explicitly are not limited. */
 } fmm_plan_options_t;
 
 /* Plan C = A*B for an m x k by k x n product with `levels` recursive steps of
@@ -270,14 +288,21 @@ typedef struct {
     double model_ms;     /* predicted time */
     double leaf_ms, add_ms;
     size_t workspace_bytes;
+    double error_bound;  /* as fmm_plan_info_t::error_bound */
 } fmm_candidate_t;
 
 /* Writes up to max candidates for (m, k, n, dtype), best predicted first,
  * restricted to base case `alg` when it is not NULL and not "auto"; *count
  * receives the number written.  Candidates whose workspace exceeds
- * budget_bytes (0 = the default budget above) are left out. */
+ * budget_bytes (0 = the default budget above) or whose error bound exceeds
+ * max_error (0 = the dtype's default of fmm_plan_options_t::max_error, < 0 =
+ * no limit) are left out.  The automatic choice ("auto", levels -1, server
+ * requests without a named plan) takes the first candidate of this list, so
+ * it never exceeds the error budget; a recorded measured choice
+ * (fmm_tune_record) above the budget is ignored. */
 fmm_status fmm_rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const char *alg,
-                               size_t budget_bytes, fmm_candidate_t *out, int max, int *count);
+                               size_t budget_bytes, double max_error, fmm_candidate_t *out, int max,
+                               int *count);
 
 /* Records a measured choice for the exact shape (m, k, n, dtype) in a
  * process-wide table: later fmm_plan calls with alg "auto" and levels -1 for
@@ -311,6 +336,9 @@ typedef struct {
     int use_graph;       /* non-zero: each batch's launches are recorded into a HIP graph
                             (kernel nodes only), instantiated once and launched as one
                             graph; the executable graph is freed when the batch completes */
+    double max_error[3]; /* per dtype (index = fmm_dtype): error budget of the automatic
+                            choice for requests without a named plan, as
+                            fmm_plan_options_t::max_error (0: default, < 0: no limit) */
 } fmm_server_options_t;
 
 typedef struct {
@@ -322,6 +350,11 @@ typedef struct {
     const void *B; int64_t ldb;
     void *C; int64_t ldc;
     void *user;          /* returned with the completion */
+    int wait_stream;     /* non-zero: the batch that runs the request first waits, on the
+                            server's stream, for the work enqueued on `stream` before the
+                            submit (an event recorded there by fmm_server_submit), e.g. the
+                            kernels that write A and B or that still use C's memory */
+    void *stream;        /* hipStream_t for wait_stream (NULL: the null stream) */
 } fmm_request_t;
 
 typedef struct {
@@ -341,8 +374,12 @@ typedef struct {
  * be allocated. */
 fmm_status fmm_server_create(fmm_server_t *out, const fmm_server_options_t *opts, void *stream);
 
-/* Queues a request (validated on the host: sizes, dtype, NULL pointers);
- * *id is its sequence number.  Does not launch anything by itself. */
+/* Queues a request; *id is its sequence number.  The request is validated on
+ * the host as fmm_multiply validates its arguments (sizes, dtype, NULL
+ * pointers, leading dimensions, C overlapping A or B) and, when it names no
+ * plan, planned by the automatic choice; an invalid request is refused here
+ * with its own status and never joins a batch.  Does not launch anything by
+ * itself. */
 fmm_status fmm_server_submit(fmm_server_t s, const fmm_request_t *req, int64_t *id);
 
 /* Makes progress: retires finished batches (frees their arena space) and

@@ -73,3 +73,45 @@ def fmm(alg, levels, A, B):
     if m0 < m:
         C[m0:, :] = gemm(A[m0:, :], B)
     return C
+
+
+def growth(alg):
+    """Root-mean-square error growth of one step of `alg` for operands with
+    i.i.d. zero-mean entries: g = sqrt(sum_r |u_r|^2 |v_r|^2 |w_r|^2 / (MKN)),
+    with u_r, v_r the columns of U, V and w_r the column of W (the C blocks
+    product r feeds).  Derivation: a block of S_r has entry variance
+    |u_r|^2 var(A) (independent blocks add variances), T_r likewise, and an
+    error in product r reaches |w_r|^2 blocks' worth of C; the classical
+    product of the same blocks has MKN such terms of unit weight, so g = 1
+    for a classical step (classical_222_8) and the ratio compounds over the
+    levels.  Strassen (Section 2.1's formulas): sum = 32, g = 2."""
+    U = np.asarray(alg.U, dtype=np.float64)
+    V = np.asarray(alg.V, dtype=np.float64)
+    W = np.asarray(alg.W, dtype=np.float64)
+    s = float(np.sum((U ** 2).sum(0) * (V ** 2).sum(0) * (W ** 2).sum(0)))
+    return float(np.sqrt(s / (alg.M * alg.K * alg.N)))
+
+
+def gate(alg, levels, k):
+    """Tolerance on the relative Frobenius error of the BF16x3 fast product
+    against the exact (binary64) product, for inner dimension k:
+
+        e0 * prod over the levels of growth(level's base case),
+        e0 = 3 * 2^-16 + (2 + sqrt(k)) * 2^-24.
+
+    e0 bounds the relative error each product term s*t carries: the two split
+    residuals |x - hi - lo| <= 2^-16 |x| (each bf16 rounding has unit
+    roundoff 2^-8), the dropped lo*lo term <= 2^-16 |s t|, the rounding of
+    the binary64 operand sums to FP32 (2^-24 each), and FP32 accumulation
+    over k terms taken as uncorrelated roundings (sqrt(k) 2^-24).  Errors of
+    distinct terms are uncorrelated, so they add in quadrature, and the
+    algorithm amplifies their root-mean-square by growth() per level.  Using
+    the worst-case per-term bound as the root-mean-square makes the gate
+    about an order of magnitude above what random inputs give."""
+    from . import recursive
+    algs = recursive._levels(alg, levels) if levels else []
+    e0 = 3.0 * 2.0 ** -16 + (2.0 + np.sqrt(max(k, 1))) * 2.0 ** -24
+    g = 1.0
+    for a in algs:
+        g *= growth(a)
+    return e0 * g

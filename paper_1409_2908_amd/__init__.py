@@ -49,24 +49,26 @@ class _Info(ctypes.Structure):
                 ("gemm_tiles", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t),
                 ("leaf_flops", ctypes.c_double), ("classical_flops", ctypes.c_double),
                 ("add_bytes", ctypes.c_double), ("gemm_min_bytes", ctypes.c_double),
-                ("fuse_levels", ctypes.c_int), ("alg", ctypes.c_char * 80), ("leaf_tile", ctypes.c_int)]
+                ("fuse_levels", ctypes.c_int), ("alg", ctypes.c_char * 80), ("leaf_tile", ctypes.c_int),
+                ("pair_form", ctypes.c_int), ("error_bound", ctypes.c_double)]
 
 
 class _Options(ctypes.Structure):
     _fields_ = [("fuse_levels", ctypes.c_int), ("host_only", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("defer_device_memory", ctypes.c_int),
-                ("leaf_tile", ctypes.c_int)]
+                ("leaf_tile", ctypes.c_int), ("max_error", ctypes.c_double)]
 
 
 class _Candidate(ctypes.Structure):
     _fields_ = [("alg", ctypes.c_char * 80), ("levels", ctypes.c_int), ("fuse_levels", ctypes.c_int),
-                ("leaf_tile", ctypes.c_int), ("model_ms", ctypes.c_double), ("leaf_ms", ctypes.c_double), ("add_ms", ctypes.c_double),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("leaf_tile", ctypes.c_int), ("model_ms", ctypes.c_double), ("leaf_ms", ctypes.c_double),
+                ("add_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t), ("error_bound", ctypes.c_double)]
 
 
 class _ServerOptions(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int),
-                ("max_inflight", ctypes.c_int), ("fuse_levels", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("max_inflight", ctypes.c_int), ("fuse_levels", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("max_error", ctypes.c_double * 3)]
 
 
 class _Request(ctypes.Structure):
@@ -74,7 +76,7 @@ class _Request(ctypes.Structure):
                 ("dtype", ctypes.c_int), ("alg", ctypes.c_char_p), ("levels", ctypes.c_int),
                 ("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("B", ctypes.c_void_p),
                 ("ldb", ctypes.c_int64), ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64),
-                ("user", ctypes.c_void_p)]
+                ("user", ctypes.c_void_p), ("wait_stream", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
 
 class _Completion(ctypes.Structure):
@@ -110,7 +112,7 @@ def _load():
                                   ctypes.POINTER(i64), i32, vp], i32),
         "fmm_plan_device_bytes": ([P], ctypes.c_size_t),
         "fmm_plan_bind": ([P, vp, ctypes.c_size_t, vp], i32),
-        "fmm_rank_candidates": ([i64, i64, i64, i32, ctypes.c_char_p, ctypes.c_size_t,
+        "fmm_rank_candidates": ([i64, i64, i64, i32, ctypes.c_char_p, ctypes.c_size_t, dp,
                                  ctypes.POINTER(_Candidate), i32, ctypes.POINTER(i32)], i32),
         "fmm_server_create": ([ctypes.POINTER(P), ctypes.POINTER(_ServerOptions), vp], i32),
         "fmm_server_submit": ([P, ctypes.POINTER(_Request), ctypes.POINTER(i64)], i32),
@@ -173,8 +175,13 @@ def _mat(t, name, elt):
         raise ValueError(f"{name} must have unit column stride (row-major)")
     if t.numel() and not t.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
+    if t.size(0) > 1 and t.numel() and t.stride(0) < t.size(1):
+        # rows would overlap (an expanded or overlapping view): the library
+        # would read or write past the tensor's storage
+        raise ValueError(f"{name} must have row stride >= its number of columns, got stride "
+                         f"{t.stride(0)} for {t.size(1)} columns")
     ld = t.stride(0) if t.size(0) > 1 else max(t.size(1), 1)
-    return ctypes.c_void_p(t.data_ptr() if t.numel() else 0), max(ld, t.size(1))
+    return ctypes.c_void_p(t.data_ptr() if t.numel() else 0), ld
 
 
 class Plan:
@@ -182,11 +189,11 @@ class Plan:
     (``fmm_plan_host``) can be inspected but not run."""
 
     def __init__(self, alg, m, k, n, levels, dtype=F64, host_only=False, fuse_levels=0,
-                 use_graph=False, defer_device_memory=False, leaf_tile=0):
+                 use_graph=False, defer_device_memory=False, leaf_tile=0, max_error=0.0):
         self._p = ctypes.c_void_p()
         self.dtype = _dtype_code(dtype)
         opts = _Options(int(fuse_levels), 1 if host_only else 0, 1 if use_graph else 0,
-                        1 if defer_device_memory else 0, int(leaf_tile))
+                        1 if defer_device_memory else 0, int(leaf_tile), float(max_error))
         _check(_lib.fmm_plan_ex(ctypes.byref(self._p), alg.encode(), m, k, n, levels, self.dtype,
                                 ctypes.byref(opts)))
         self.m, self.k, self.n = m, k, n
@@ -336,12 +343,13 @@ def multiply_batched(plans, As, Bs, Cs=None, stream=None):
     return outs
 
 
-def rank_candidates(m, k, n, dtype=F64, alg=None, budget_bytes=0, max_count=64):
-    """The cost model's candidates (fmm_rank_candidates), best predicted first."""
+def rank_candidates(m, k, n, dtype=F64, alg=None, budget_bytes=0, max_count=64, max_error=0.0):
+    """The cost model's candidates (fmm_rank_candidates), best predicted first;
+    max_error 0 applies the dtype's default error budget, < 0 none."""
     out = (_Candidate * max_count)()
     cnt = ctypes.c_int()
     _check(_lib.fmm_rank_candidates(m, k, n, _dtype_code(dtype), alg.encode() if alg else None,
-                                    int(budget_bytes), out, max_count, ctypes.byref(cnt)))
+                                    int(budget_bytes), float(max_error), out, max_count, ctypes.byref(cnt)))
     res = []
     for c in out[:cnt.value]:
         d = {f: getattr(c, f) for f, _ in _Candidate._fields_}
@@ -354,16 +362,19 @@ class Server:
     """Continuous-batching request server (fmm_server_*).  Keeps the operand
     tensors of every request alive until its completion has been returned."""
 
-    def __init__(self, arena_bytes, max_batch=8, max_inflight=2, fuse_levels=0, stream=None, use_graph=False):
+    def __init__(self, arena_bytes, max_batch=8, max_inflight=2, fuse_levels=0, stream=None, use_graph=False,
+                 max_error=(0.0, 0.0, 0.0)):
         self._s = ctypes.c_void_p()
         opts = _ServerOptions(int(arena_bytes), int(max_batch), int(max_inflight), int(fuse_levels),
-                              1 if use_graph else 0)
+                              1 if use_graph else 0, (ctypes.c_double * 3)(*[float(x) for x in max_error]))
         sp = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
         _check(_lib.fmm_server_create(ctypes.byref(self._s), ctypes.byref(opts), sp))
         self._live = {}
 
-    def submit(self, A, B, C=None, dtype=None, alg=None, levels=-1):
-        """Queue C = A @ B; returns (request id, C)."""
+    def submit(self, A, B, C=None, dtype=None, alg=None, levels=-1, stream=None):
+        """Queue C = A @ B; returns (request id, C).  The request's batch runs
+        after the work enqueued so far on `stream` (default: torch's current
+        stream), which made A and B and last used C's memory."""
         import torch
         if dtype is None:
             dtype = F64 if A.dtype == torch.float64 else F32
@@ -377,7 +388,7 @@ class Server:
         b, ldb = _mat(B, "B", elt)
         c, ldc = _mat(C, "C", elt)
         algb = alg.encode() if alg else None
-        req = _Request(m, k, n, dtype, algb, int(levels), a, lda, b, ldb, c, ldc, None)
+        req = _Request(m, k, n, dtype, algb, int(levels), a, lda, b, ldb, c, ldc, None, 1, _stream_ptr(stream))
         rid = ctypes.c_int64()
         _check(_lib.fmm_server_submit(self._s, ctypes.byref(req), ctypes.byref(rid)))
         self._live[rid.value] = (A, B, C)

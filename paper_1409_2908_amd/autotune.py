@@ -67,17 +67,19 @@ def _time_plan(p, A, B, C, reps, warmup):
     return e0.elapsed_time(e1) / reps
 
 
-def tune(m, k, n, dtype=F64, top=4, reps=3, warmup=1, cache=None, budget_bytes=0, seed=0):
+def tune(m, k, n, dtype=F64, top=4, reps=3, warmup=1, cache=None, budget_bytes=0, seed=0, max_error=0.0):
     """Time the model's `top` candidates (and the classical product) for the
     shape on the current device, each with one and two levels per addition
     pass where both exist and, on the FP64 / FP32 paths, with 64 x 64 and
     128 x 128 leaf tiles; record and return the fastest as a dict
     {alg, levels, fuse_levels, leaf_tile, ms, tflops, candidates: [...]},
-    where each candidate carries its model prediction and measured ms."""
+    where each candidate carries its model prediction and measured ms.
+    Only candidates within the error budget `max_error` (0: the dtype's
+    default, < 0: none) are timed, as for the automatic choice."""
     import torch
     dtype = _dtype_code(dtype)
     elt = torch.float64 if dtype == F64 else torch.float32
-    cands = rank_candidates(m, k, n, dtype, budget_bytes=budget_bytes)
+    cands = rank_candidates(m, k, n, dtype, budget_bytes=budget_bytes, max_error=max_error)
     trial = cands[:top]
     if not any(c["alg"] == "classical" for c in trial):
         trial += [c for c in cands if c["alg"] == "classical"]

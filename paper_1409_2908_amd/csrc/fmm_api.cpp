@@ -97,22 +97,9 @@ size_t span_bytes(int64_t rows, int64_t cols, int64_t ld, size_t es) {
 
 fmm_status validate(const fmm::Plan& P, const void* A, int64_t lda, const void* B, int64_t ldb,
                     const void* C, int64_t ldc) {
-  if (P.m == 0 || P.n == 0) return FMM_OK;
-  if (!C) return fail(FMM_EINVAL, "C is NULL");
-  if (ldc < P.n) return fail(FMM_EINVAL, "ldc < n");
-  // The leaf kernels address a 128-row tile with 32-bit byte offsets.
-  if (lda >= kMaxLd || ldb >= kMaxLd || ldc >= kMaxLd)
-    return fail(FMM_EUNSUPPORTED, "leading dimensions must be below 2^21 elements");
-  if (P.k > 0) {
-    if (!A || !B) return fail(FMM_EINVAL, "A or B is NULL");
-    if (lda < P.k) return fail(FMM_EINVAL, "lda < k");
-    if (ldb < P.n) return fail(FMM_EINVAL, "ldb < n");
-    const size_t es = elt_size(P.elt);
-    const size_t cb = span_bytes(P.m, P.n, ldc, es);
-    if (overlaps(C, cb, A, span_bytes(P.m, P.k, lda, es)) || overlaps(C, cb, B, span_bytes(P.k, P.n, ldb, es)))
-      return fail(FMM_EINVAL, "C overlaps A or B");
-  }
-  return FMM_OK;
+  std::string why;
+  const int st = fmm::check_operands(P.m, P.k, P.n, elt_size(P.elt), A, lda, B, ldb, C, ldc, &why);
+  return st ? fail((fmm_status)st, why) : FMM_OK;
 }
 
 fmm::Bases make_bases(const fmm::Plan& P, const void* A, int64_t lda, const void* B, int64_t ldb,
@@ -321,7 +308,7 @@ fmm_status scratch_ptr(int dev, void** out) {
 
 fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
                        int dtype, int fuse, bool device, bool defer = false, bool graph = false,
-                       int leaf_tile = 0) {
+                       int leaf_tile = 0, double max_error = 0) {
   if (!out) return fail(FMM_EINVAL, "out is NULL");
   *out = nullptr;
   if (leaf_tile != 0 && leaf_tile != 64 && leaf_tile != 128) return fail(FMM_EINVAL, "leaf_tile must be 0, 64 or 128");
@@ -335,7 +322,7 @@ fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
     if (levels < -1) return fail(FMM_EINVAL, "levels must be >= -1");
     fmm::Candidate pick;
     std::string why;
-    if (!fmm::choose(m, k, n, dtype, alg, levels, 0, fuse, &pick, &why))
+    if (!fmm::choose(m, k, n, dtype, alg, levels, 0, fuse, max_error, &pick, &why))
       return fail(why.rfind("unknown algorithm", 0) == 0 ? FMM_EALG
                   : why.rfind("no candidate", 0) == 0    ? FMM_ENOMEM
                                                          : FMM_EINVAL,
@@ -356,16 +343,6 @@ fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
   }
   fmm::Plan& P = h->P;
   P.leaf_tile = leaf_tile;
-  // Small one-level plans form S and T in one launch: between two dependent
-  // launches the queue idles about as long as one such pass takes.
-  if (P.s_passes.size() == 1 && P.t_passes.size() == 1) {
-    const fmm::FormPass& fs = P.s_passes[0];
-    const fmm::FormPass& ft = P.t_passes[0];
-    P.pair_form = fs.lv == 1 && ft.lv == 1 && fs.alg == ft.alg && fs.out_elt != fmm::ELT_BF16X2 &&
-                  ft.out_elt != fmm::ELT_BF16X2 && fs.h > 0 && fs.w > 0 && ft.h > 0 && ft.w > 0 &&
-                  fs.ngroups > 0 && ft.ngroups > 0 &&
-                  fs.h * fs.w * fs.ngroups + ft.h * ft.w * ft.ngroups <= (int64_t(1) << 20);
-  }
   if (device) {
     if (const char* bud = std::getenv("FMM_HBM_BUDGET")) {
       const double budget = std::atof(bud);
@@ -421,6 +398,25 @@ fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
 
 namespace fmm {
 int set_error(int code, const std::string& msg) { return (int)fail((fmm_status)code, msg); }
+
+int check_operands(int64_t m, int64_t k, int64_t n, size_t es, const void* A, int64_t lda, const void* B,
+                   int64_t ldb, const void* C, int64_t ldc, std::string* why) {
+  if (m == 0 || n == 0) return FMM_OK;
+  if (!C) return *why = "C is NULL", FMM_EINVAL;
+  if (ldc < n) return *why = "ldc < n", FMM_EINVAL;
+  // The leaf kernels address a 128-row tile with 32-bit byte offsets.
+  if (lda >= kMaxLd || ldb >= kMaxLd || ldc >= kMaxLd)
+    return *why = "leading dimensions must be below 2^21 elements", FMM_EUNSUPPORTED;
+  if (k > 0) {
+    if (!A || !B) return *why = "A or B is NULL", FMM_EINVAL;
+    if (lda < k) return *why = "lda < k", FMM_EINVAL;
+    if (ldb < n) return *why = "ldb < n", FMM_EINVAL;
+    const size_t cb = span_bytes(m, n, ldc, es);
+    if (overlaps(C, cb, A, span_bytes(m, k, lda, es)) || overlaps(C, cb, B, span_bytes(k, n, ldb, es)))
+      return *why = "C overlaps A or B", FMM_EINVAL;
+  }
+  return FMM_OK;
+}
 }  // namespace fmm
 
 extern "C" {
@@ -442,7 +438,8 @@ fmm_status fmm_plan_ex(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
   const bool defer = opts && opts->defer_device_memory;
   const bool graph = opts && opts->use_graph;
   const int tile = opts ? opts->leaf_tile : 0;
-  return plan_common(out, alg, m, k, n, levels, dtype, fuse, !host_only, defer, graph, tile);
+  const double max_error = opts ? opts->max_error : 0;
+  return plan_common(out, alg, m, k, n, levels, dtype, fuse, !host_only, defer, graph, tile, max_error);
 }
 
 size_t fmm_plan_device_bytes(fmm_plan_t p) {
@@ -710,6 +707,8 @@ fmm_status fmm_plan_info(fmm_plan_t p, fmm_plan_info_t* info) {
   std::snprintf(info->alg, sizeof(info->alg), "%s",
                 P.alg_id < 0 ? "classical" : mixed ? P.alg_name.c_str() : fmm::alg_info(P.alg_id).name);
   info->leaf_tile = P.leaf_tile;
+  info->pair_form = P.pair_form ? 1 : 0;
+  info->error_bound = fmm::error_bound(P.levels > 0 ? P.lv_alg : std::vector<int>(), P.k, P.dtype);
   return FMM_OK;
 }
 
@@ -806,13 +805,14 @@ fmm_status fmm_check_algorithms(void) {
 }
 
 fmm_status fmm_rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const char* alg,
-                               size_t budget_bytes, fmm_candidate_t* out, int max, int* count) {
+                               size_t budget_bytes, double max_error, fmm_candidate_t* out, int max,
+                               int* count) {
   if (count) *count = 0;
   if (max < 0 || (max > 0 && !out)) return fail(FMM_EINVAL, "bad output array");
   fmm_status st = check_tables_once();
   if (st != FMM_OK) return st;
   std::vector<fmm::Candidate> cands;
-  std::string why = fmm::rank_candidates(m, k, n, dtype, alg, budget_bytes, 0, cands);
+  std::string why = fmm::rank_candidates(m, k, n, dtype, alg, budget_bytes, 0, max_error, cands);
   if (!why.empty()) return fail(why.rfind("unknown algorithm", 0) == 0 ? FMM_EALG : FMM_EINVAL, why);
   const int nout = std::min<int>(max, (int)cands.size());
   for (int i = 0; i < nout; ++i) {
@@ -825,6 +825,7 @@ fmm_status fmm_rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const
     out[i].leaf_ms = cands[i].leaf_ms;
     out[i].add_ms = cands[i].add_ms;
     out[i].workspace_bytes = cands[i].ws_bytes;
+    out[i].error_bound = cands[i].err;
   }
   if (count) *count = nout;
   return FMM_OK;

@@ -215,7 +215,12 @@ struct PlanSummary {
   double add_bytes = 0, leaf_flops = 0;
   size_t ws_bytes = 0;
   int form_passes = 0, comb_passes = 0;
+  bool pair_form = false;  // S and T formed by one launch (Plan::pair_form)
 };
+
+// Plans of one level whose S and T passes together cover at most this many
+// output positions form both in one launch (Plan::pair_form).
+constexpr int64_t kPairFormMaxPositions = int64_t(1) << 20;
 std::string summarize_plan(PlanSummary& S, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
                            int dtype, int fuse);
 
@@ -230,7 +235,34 @@ struct Candidate {
   int tile = 0;  // leaf tile edge of a recorded choice; 0: chosen per launch
   double model_ms = 0, leaf_ms = 0, add_ms = 0;
   size_t ws_bytes = 0;
+  double err = 0;  // predicted error bound (error_bound)
 };
+
+// Root-mean-square growth of the rounding error per recursive step of base
+// case `id`, for operands with i.i.d. zero-mean entries:
+//   sqrt(sum_r |u_r|^2 |v_r|^2 |w_r|^2 / (M K N))
+// (u_r, v_r: columns r of U and V; w_r: column r of W).  1 for a classical
+// step, 2 for Strassen.
+double growth(int id);
+
+// Predicted bound on the relative Frobenius error of C against the exact
+// product for a plan whose levels use the base cases `ids` (top first; empty
+// for the classical product), inner dimension k and dtype:
+//   e0 * prod growth(ids),  e0 = c + (2 + sqrt(k)) u
+// with u the unit roundoff of the leaf arithmetic (2^-53 FP64, 2^-24 FP32)
+// and c = 3 * 2^-16 on the BF16x3 path (two split residuals and the dropped
+// lo*lo term per product term), 0 otherwise.
+double error_bound(const std::vector<int>& ids, int64_t k, int dtype);
+
+// Largest error bound the automatic choice accepts for dtype when the caller
+// gives 0: 1e-12 (FP64), 1e-4 (FP32), 5e-4 (BF16x3).
+double default_max_error(int dtype);
+
+// Argument checks of one product C = A*B (m x k by k x n, element size es):
+// leading dimensions, NULL pointers with non-zero sizes, C overlapping A or
+// B.  0 when valid, else an fmm_status with *why set.
+int check_operands(int64_t m, int64_t k, int64_t n, size_t es, const void* A, int64_t lda, const void* B,
+                   int64_t ldb, const void* C, int64_t ldc, std::string* why);
 
 // Workspace budget: FMM_HBM_BUDGET (bytes) if set, else 3/4 of the current
 // device's free memory, else 3/4 of 288 GB.
@@ -238,9 +270,11 @@ size_t default_budget();
 
 // Candidates for (m, k, n, dtype), best predicted first; alg NULL or "auto"
 // for every base case, else only that one ("classical" gives the plain GEMM).
-// Returns an error message or "".
+// Candidates whose workspace exceeds `budget` (0: default_budget) or whose
+// error bound exceeds `max_error` (0: default_max_error, < 0: no limit) are
+// left out.  Returns an error message or "".
 std::string rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const char* alg, size_t budget,
-                            int fuse, std::vector<Candidate>& out);
+                            int fuse, double max_error, std::vector<Candidate>& out);
 
 // Measured choices recorded by an autotuner (fmm_tune_record), keyed by the
 // exact (m, k, n, dtype).
@@ -250,10 +284,10 @@ void clear_tuned();
 
 // The plan to make for alg ("auto"/NULL = any base case) at `levels` (-1 =
 // any depth): a recorded measured choice when alg is "auto" and levels -1 and
-// one exists for the shape (and fits the budget), else the model's best.
-// False with *why on failure.
+// one exists for the shape (and fits the budget and max_error), else the
+// model's best within both.  False with *why on failure.
 bool choose(int64_t m, int64_t k, int64_t n, int dtype, const char* alg, int levels, size_t budget, int fuse,
-            Candidate* pick, std::string* why);
+            double max_error, Candidate* pick, std::string* why);
 
 constexpr int64_t kTileM = 128, kTileN = 128;
 

@@ -346,6 +346,9 @@ std::string summarize_plan(PlanSummary& S, const char* alg, int64_t m, int64_t k
       depth = d2;
     }
     S.ws_bytes = ws.used;
+    // the condition make_plan applies: one unsplit pass per side of one level
+    S.pair_form = L == 1 && dtype != 2 && S.form_passes == 2 &&
+                  (m0 / fm) * (k0 / fk) + (k0 / fk) * (n0 / fn) <= kPairFormMaxPositions;
   }
   for (GemmGroup& g : S.groups) {
     g.tiles_m = (g.m + kTileM - 1) / kTileM;
@@ -607,6 +610,16 @@ std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n,
   P.gemm_tiles = tiles;
   P.add_bytes = add_bytes;
   P.ws_bytes = ws.used;
+  // Small one-level plans form S and T in one launch: between two dependent
+  // launches the queue idles about as long as one such pass takes.
+  if (P.s_passes.size() == 1 && P.t_passes.size() == 1) {
+    const FormPass& fs = P.s_passes[0];
+    const FormPass& ft = P.t_passes[0];
+    P.pair_form = fs.lv == 1 && ft.lv == 1 && fs.alg == ft.alg && fs.out_elt != ELT_BF16X2 &&
+                  ft.out_elt != ELT_BF16X2 && fs.h > 0 && fs.w > 0 && ft.h > 0 && ft.w > 0 &&
+                  fs.ngroups > 0 && ft.ngroups > 0 &&
+                  fs.h * fs.w * fs.ngroups + ft.h * ft.w * ft.ngroups <= kPairFormMaxPositions;
+  }
 
   // Host image of the device descriptor table.
   Arena tab;

@@ -73,6 +73,7 @@ struct Queued {
   int levels;
   double submit_ms;
   fmm_plan_t plan = nullptr;  // made once, kept while the request waits for room
+  hipEvent_t ready = nullptr; // recorded on the request's stream at submit (NULL: none)
 };
 
 struct Admitted {
@@ -202,6 +203,26 @@ fmm_status launch_graph(fmm_server_s& S, Batch& b, std::vector<fmm_plan_t>& plan
   return FMM_OK;
 }
 
+// An event of the server's pool (created when the pool is empty).
+fmm_status take_event(fmm_server_s& S, hipEvent_t* ev) {
+  if (S.spare_events.empty()) {
+    hipEvent_t e0;
+    hipError_t e = hipEventCreateWithFlags(&e0, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(FMM_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+    S.spare_events.push_back(e0);
+  }
+  *ev = S.spare_events.back();
+  S.spare_events.pop_back();
+  return FMM_OK;
+}
+
+// Returns a queued request's stream event to the pool (a wait on it that was
+// already enqueued keeps the state the event had then).
+void drop_ready(fmm_server_s& S, Queued& q) {
+  if (q.ready) S.spare_events.push_back(q.ready);
+  q.ready = nullptr;
+}
+
 // Admits and launches batches while there is room.
 fmm_status admit(fmm_server_s& S) {
   const size_t arena_bytes = S.opt.arena_bytes;
@@ -217,6 +238,7 @@ fmm_status admit(fmm_server_s& S) {
         o.defer_device_memory = 1;
         fmm_status st = fmm_plan_ex(&q.plan, q.alg.c_str(), q.r.m, q.r.k, q.r.n, q.levels, q.r.dtype, &o);
         if (st != FMM_OK) {
+          drop_ready(S, q);
           complete(S, q.id, q.r.user, st, q.submit_ms, S.now_ms(), 0, q.alg, q.levels);
           S.queue.pop_front();
           continue;
@@ -225,6 +247,7 @@ fmm_status admit(fmm_server_s& S) {
       const size_t bytes = fmm_plan_device_bytes(q.plan);
       if (bytes > arena_bytes) {
         (void)fmm_plan_destroy(q.plan);
+        drop_ready(S, q);
         complete(S, q.id, q.r.user, FMM_ENOMEM, q.submit_ms, S.now_ms(), 0, q.alg, q.levels);
         S.queue.pop_front();
         continue;
@@ -233,6 +256,17 @@ fmm_status admit(fmm_server_s& S) {
       if (!S.arena.alloc(bytes, &off)) {
         blocked = true;  // first come, first served: wait for arena space
         break;
+      }
+      // the batch runs after the work the request's stream had enqueued at submit
+      if (q.ready) {
+        hipError_t we = hipStreamWaitEvent(S.stream, q.ready, 0);
+        drop_ready(S, q);
+        if (we != hipSuccess) {
+          (void)fmm_plan_destroy(q.plan);
+          complete(S, q.id, q.r.user, FMM_EHIP, q.submit_ms, S.now_ms(), 0, q.alg, q.levels);
+          S.queue.pop_front();
+          continue;
+        }
       }
       fmm_status st = fmm_plan_bind(q.plan, S.arena_mem + off, bytes, S.stream);
       if (st != FMM_OK) {
@@ -261,14 +295,10 @@ fmm_status admit(fmm_server_s& S) {
       ldb[i] = r.ldb;
       ldc[i] = r.ldc;
     }
-    if (S.spare_events.empty()) {
-      hipEvent_t ev;
-      hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-      if (e != hipSuccess) return fail(FMM_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
-      S.spare_events.push_back(ev);
+    {
+      const fmm_status est = take_event(S, &b.ev);
+      if (est != FMM_OK) return est;
     }
-    b.ev = S.spare_events.back();
-    S.spare_events.pop_back();
     b.launch_ms = S.now_ms();
     fmm_status st = S.opt.use_graph
                         ? launch_graph(S, b, plans, A, lda, B, ldb, C, ldc)
@@ -328,10 +358,15 @@ fmm_status fmm_server_submit(fmm_server_t s, const fmm_request_t* req, int64_t* 
   const fmm_request_t& r = *req;
   if (r.m < 0 || r.k < 0 || r.n < 0) return fail(FMM_EINVAL, "sizes must be non-negative");
   if (r.dtype < 0 || r.dtype > 2) return fail(FMM_EINVAL, "unknown dtype");
-  if (r.m > 0 && r.n > 0 && (!r.C || (r.k > 0 && (!r.A || !r.B))))
-    return fail(FMM_EINVAL, "NULL operand");
+  {
+    // the checks fmm_multiply_batched makes, per request: a request that
+    // would fail them is refused here and never makes its batch fail
+    std::string why;
+    const int st = fmm::check_operands(r.m, r.k, r.n, r.dtype == FMM_F64 ? 8 : 4, r.A, r.lda, r.B, r.ldb, r.C,
+                                       r.ldc, &why);
+    if (st) return fail((fmm_status)st, why);
+  }
   Queued q;
-  q.id = s->next_id++;
   q.r = r;
   q.submit_ms = s->now_ms();
   const bool auto_alg = !r.alg || !std::strcmp(r.alg, "auto");
@@ -340,7 +375,7 @@ fmm_status fmm_server_submit(fmm_server_t s, const fmm_request_t* req, int64_t* 
     fmm::Candidate pick;
     std::string why;
     if (!fmm::choose(r.m, r.k, r.n, r.dtype, auto_alg ? nullptr : r.alg, r.levels, s->opt.arena_bytes,
-                     s->opt.fuse_levels, &pick, &why))
+                     s->opt.fuse_levels, s->opt.max_error[r.dtype], &pick, &why))
       return fail(why.rfind("no candidate", 0) == 0 ? FMM_ENOMEM : FMM_EINVAL, why);
     q.alg = pick.alg;
     q.levels = pick.levels;
@@ -348,6 +383,16 @@ fmm_status fmm_server_submit(fmm_server_t s, const fmm_request_t* req, int64_t* 
     q.alg = r.alg;
     q.levels = r.levels;
   }
+  if (r.wait_stream && (hipStream_t)r.stream != s->stream) {
+    fmm_status est = take_event(*s, &q.ready);
+    if (est != FMM_OK) return est;
+    hipError_t e = hipEventRecord(q.ready, (hipStream_t)r.stream);
+    if (e != hipSuccess) {
+      drop_ready(*s, q);
+      return fail(FMM_EHIP, std::string("hipEventRecord on the request's stream: ") + hipGetErrorString(e));
+    }
+  }
+  q.id = s->next_id++;
   s->queue.push_back(q);
   ++s->pending;
   if (id) *id = q.id;
@@ -391,8 +436,10 @@ fmm_status fmm_server_destroy(fmm_server_t s) {
     (void)hipEventDestroy(b.ev);
     if (b.exec) (void)hipGraphExecDestroy(b.exec);
   }
-  for (Queued& q : s->queue)
+  for (Queued& q : s->queue) {
     if (q.plan) (void)fmm_plan_destroy(q.plan);
+    if (q.ready) (void)hipEventDestroy(q.ready);
+  }
   for (hipEvent_t ev : s->spare_events) (void)hipEventDestroy(ev);
   if (s->arena_mem) (void)hipFree(s->arena_mem);
   if (s->own_stream) (void)hipStreamDestroy(s->stream);

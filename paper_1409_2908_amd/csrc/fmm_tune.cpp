@@ -91,7 +91,8 @@ void predict(const PlanSummary& P, int dtype, Candidate& c) {
     leaf_s = waves_time(units, wmax, tiles, kSlots / kCUs, (double)kTileM, ref);
   }
   const double add_s = P.add_bytes / kAddBw;
-  const double launches = 1.0 + P.form_passes + P.comb_passes;
+  // a pair-formed plan forms S and T in one launch
+  const double launches = 1.0 + P.form_passes + P.comb_passes - (P.pair_form ? 1 : 0);
   c.leaf_ms = leaf_s * 1e3;
   c.add_ms = add_s * 1e3;
   c.model_ms = (leaf_s + add_s + launches * kLaunch) * 1e3;
@@ -99,6 +100,31 @@ void predict(const PlanSummary& P, int dtype, Candidate& c) {
 }
 
 }  // namespace
+
+double growth(int id) {
+  const AlgInfo& a = alg_info(id);
+  const int MK = a.M * a.K, KN = a.K * a.N, MN = a.M * a.N;
+  double s = 0;
+  for (int r = 0; r < a.R; ++r) {
+    double u = 0, v = 0, w = 0;
+    for (int i = 0; i < MK; ++i) u += (double)a.U[i * a.R + r] * a.U[i * a.R + r];
+    for (int j = 0; j < KN; ++j) v += (double)a.V[j * a.R + r] * a.V[j * a.R + r];
+    for (int k = 0; k < MN; ++k) w += (double)a.W[k * a.R + r] * a.W[k * a.R + r];
+    s += u * v * w;
+  }
+  return std::sqrt(s / ((double)a.M * a.K * a.N));
+}
+
+double error_bound(const std::vector<int>& ids, int64_t k, int dtype) {
+  const double sk = 2.0 + std::sqrt((double)std::max<int64_t>(k, 1));
+  double e = dtype == 0 ? sk * std::ldexp(1.0, -53)
+             : dtype == 1 ? sk * std::ldexp(1.0, -24)
+                          : 3.0 * std::ldexp(1.0, -16) + sk * std::ldexp(1.0, -24);
+  for (int id : ids) e *= growth(id);
+  return e;
+}
+
+double default_max_error(int dtype) { return dtype == 0 ? 1e-12 : dtype == 1 ? 1e-4 : 5e-4; }
 
 size_t default_budget() {
   if (const char* b = std::getenv("FMM_HBM_BUDGET")) {
@@ -114,11 +140,12 @@ size_t default_budget() {
 }
 
 std::string rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const char* alg, size_t budget,
-                            int fuse, std::vector<Candidate>& out) {
+                            int fuse, double max_error, std::vector<Candidate>& out) {
   out.clear();
   if (m < 0 || k < 0 || n < 0) return "sizes must be non-negative";
   if (dtype < 0 || dtype > 2) return "unknown dtype";
   if (!budget) budget = default_budget();
+  if (max_error == 0) max_error = default_max_error(dtype);
   const bool any = !alg || !std::strcmp(alg, "auto");
   const bool listed = !any && std::strchr(alg, '+');  // one base case per level
   std::vector<int> ids;
@@ -134,7 +161,13 @@ std::string rank_candidates(int64_t m, int64_t k, int64_t n, int dtype, const ch
     PlanSummary P;
     if (!summarize_plan(P, name, m, k, n, levels, dtype, fuse).empty()) return;
     if (P.ws_bytes > budget) return;
+    std::vector<int> lv;
+    std::string perr;
+    if (parse_levels(name, levels, &lv, &perr) > 0) return;
+    const double err = error_bound(P.levels > 0 ? lv : std::vector<int>(), k, dtype);
+    if (max_error > 0 && err > max_error) return;
     Candidate c;
+    c.err = err;
     std::snprintf(c.alg, sizeof(c.alg), "%s", name);
     c.levels = levels;
     c.fuse = P.levels > 0 ? P.fuse : 0;
@@ -210,28 +243,32 @@ void clear_tuned() {
 }
 
 bool choose(int64_t m, int64_t k, int64_t n, int dtype, const char* alg, int levels, size_t budget, int fuse,
-            Candidate* pick, std::string* why) {
+            double max_error, Candidate* pick, std::string* why) {
   const bool any = !alg || !std::strcmp(alg, "auto");
+  const double limit = max_error == 0 ? default_max_error(dtype) : max_error;
   if (any && levels < 0) {
     Candidate c;
     if (lookup_tuned(m, k, n, dtype, &c)) {
       PlanSummary P;
+      std::vector<int> lv;
+      std::string perr;
       if (summarize_plan(P, c.alg, m, k, n, c.levels, dtype, c.fuse).empty() &&
-          P.ws_bytes <= (budget ? budget : default_budget())) {
+          P.ws_bytes <= (budget ? budget : default_budget()) && parse_levels(c.alg, c.levels, &lv, &perr) <= 0 &&
+          (limit < 0 || error_bound(P.levels > 0 ? lv : std::vector<int>(), k, dtype) <= limit)) {
         *pick = c;
         return true;
       }
     }
   }
   std::vector<Candidate> cands;
-  *why = rank_candidates(m, k, n, dtype, alg, budget, fuse, cands);
+  *why = rank_candidates(m, k, n, dtype, alg, budget, fuse, max_error, cands);
   if (!why->empty()) return false;
   for (const Candidate& c : cands)
     if (levels < 0 || c.levels == levels) {
       *pick = c;
       return true;
     }
-  *why = "no candidate fits the workspace budget";
+  *why = "no candidate fits the workspace budget and the error budget";
   return false;
 }
 

@@ -7,7 +7,8 @@ Every result is compared bit for bit with the same plan run alone and eagerly
 recorded), and against the oracle to the path's tolerance:
   FP64   relF <= 1e-12
   FP32   relF <= 2e-6 * 2^L
-  BF16x3 relF <= 2e-6 * 2^L against the emulated fast algorithm
+  BF16x3 relF <= 2e-6 * 2^L against the emulated fast algorithm, and
+         relF <= oracle.bf16x3.gate(alg, L, k) against the binary64 product
 """
 import numpy as np
 import pytest
@@ -39,9 +40,10 @@ def _check_oracle(F, alg, L, A, B, C, dtype):
         assert relf(C, ref) <= 2e-6 * 2 ** L
     else:
         levels = [algorithms.get(x) for x in alg.split("+")] if "+" in alg else None
-        emu = (bf16x3.gemm(A, B) if alg == "classical"
-               else bf16x3.fmm(levels if levels else algorithms.get(alg), L, A, B))
+        algs = levels if levels else (None if alg == "classical" else algorithms.get(alg))
+        emu = bf16x3.gemm(A, B) if algs is None else bf16x3.fmm(algs, L, A, B)
         assert relf(C, emu) <= 2e-6 * 2 ** max(L, 1)
+        assert relf(C, ref) <= bf16x3.gate(algs, L if algs is not None else 0, A.shape[1])
 
 
 def _alone(F, alg, L, A, B, dtype):
@@ -232,3 +234,37 @@ def test_batched_mixed_levels_and_graph(F):
         outs = [to_host(p.multiply(dA, dB)) for _ in range(3)]
     for o in outs:
         assert np.array_equal(o, _alone(F, alg, L, A, B, dt))
+
+
+def test_autotune_records_and_auto_plans_it(F, tmp_path):
+    """The measured tuner times the model's best candidates on the device,
+    records the fastest; an "auto" plan of that shape then is the recorded
+    choice (base case, depth, fusion, tile), and it matches the oracle.  The
+    JSON cache replays the same choice into a cleared table."""
+    import torch
+    from paper_1409_2908_amd import autotune
+    m, k, n = 3000, 2048, 2500
+    say(f"case autotune {m}x{k}x{n}")
+    cache = str(tmp_path / "tune.json")
+    try:
+        autotune.clear()
+        t = autotune.tune(m, k, n, F.F64, top=3, reps=2, cache=cache)
+        say(f"  tuned {t['alg']} L={t['levels']} fuse={t['fuse_levels']} tile={t['leaf_tile']} "
+            f"{t['ms']:.3f} ms; {len(t['candidates'])} timed")
+        ok = [c for c in t["candidates"] if c["ms"] is not None]
+        assert len(ok) >= 3 and t["ms"] == min(c["ms"] for c in ok)
+        A, B = fmm_inputs.operands(61, m, k, n, "uniform")
+        with F.Plan("auto", m, k, n, -1, F.F64) as p:
+            inf = p.info
+            assert (inf["alg"], inf["levels"], inf["leaf_tile"]) == (t["alg"], t["levels"], t["leaf_tile"])
+            if t["levels"] > 0:
+                assert inf["fuse_levels"] == t["fuse_levels"]
+            C = to_host(p.multiply(to_dev(A), to_dev(B)))
+        assert relf(C, classical.gemm(A, B)) <= 1e-12
+        autotune.clear()
+        assert autotune.load_cache(cache) == 1
+        with F.Plan("auto", m, k, n, -1, F.F64, host_only=True) as p:
+            assert (p.info["alg"], p.info["levels"]) == (t["alg"], t["levels"])
+    finally:
+        autotune.clear()
+    torch.cuda.synchronize()

@@ -211,8 +211,8 @@ def test_argument_errors_before_any_device_call():
     assert lib.fmm_plan_device_bytes(None) == 0
     # ranking: negative capacity is an error, zero capacity returns nothing
     cnt = ctypes.c_int(-1)
-    assert lib.fmm_rank_candidates(64, 64, 64, 0, None, 0, None, -1, ctypes.byref(cnt)) == 1
-    assert lib.fmm_rank_candidates(64, 64, 64, 0, None, 0, None, 0, ctypes.byref(cnt)) == 0 and cnt.value == 0
+    assert lib.fmm_rank_candidates(64, 64, 64, 0, None, 0, 0.0, None, -1, ctypes.byref(cnt)) == 1
+    assert lib.fmm_rank_candidates(64, 64, 64, 0, None, 0, 0.0, None, 0, ctypes.byref(cnt)) == 0 and cnt.value == 0
     # server options
     srv = vp()
     for arena, batch, inflight in ((0, 8, 2), (1 << 20, 0, 2), (1 << 20, 65, 2), (1 << 20, 8, 0)):

@@ -423,3 +423,69 @@ def test_bf16x3_fast_emulation_exact_on_small_integers(alg, L):
     assert np.array_equal(bf16x3.fmm(a, L, A, B), A.astype(np.float64) @ B.astype(np.float64))
     # at zero levels it is the emulated classical product
     assert np.array_equal(bf16x3.fmm(a, 0, A, B), bf16x3.gemm(A, B))
+
+
+# --- the BF16x3 error gate --------------------------------------------------
+
+def test_bf16x3_growth_closed_forms_and_invariants():
+    """growth() is 1 for a classical step and 2 for Strassen (Section 2.1's
+    formulas: the seven products have |u|^2 |v|^2 |w|^2 = 8, 4, 4, 4, 4, 4, 4,
+    sum 32 over MKN = 8); it is unchanged by the permutations of Propositions
+    2.1 and 2.2 (they permute the entries of each column) and multiplies
+    under composition (Kronecker factors' norms multiply)."""
+    from oracle import bf16x3
+    assert bf16x3.growth(algorithms.get("classical_222_8")) == 1.0
+    assert bf16x3.growth(algorithms.get("strassen_222_7")) == 2.0
+    for name in ALGS:
+        a = algorithms.get(name)
+        for prop in (tensor.prop21, tensor.prop22):
+            U, V, W, (M, K, N) = prop(a.U, a.V, a.W, a.M, a.K, a.N)
+            b = algorithms.Algorithm("perm", M, K, N, a.R, tuple(map(tuple, U)), tuple(map(tuple, V)),
+                                     tuple(map(tuple, W)))
+            assert bf16x3.growth(b) == pytest.approx(bf16x3.growth(a), rel=1e-15)
+    s, t = algorithms.get("strassen_222_7"), algorithms.get("fmm_323_15")
+    assert bf16x3.growth(algorithms.compose(s, t)) == pytest.approx(
+        bf16x3.growth(s) * bf16x3.growth(t), rel=1e-14)
+    assert bf16x3.gate(s, 2, 100) == pytest.approx(bf16x3.gate([s, s], 2, 100), rel=1e-15)
+    assert bf16x3.gate(s, 0, 100) == pytest.approx(3 * 2 ** -16 + 12 * 2 ** -24, rel=1e-15)
+
+
+@pytest.mark.parametrize("name", ALGS)
+@pytest.mark.parametrize("L", [1, 2])
+@pytest.mark.parametrize("kind", ["uniform", "normal_rowscaled"])
+def test_bf16x3_gate_bounds_the_emulated_error(name, L, kind):
+    """The emulated BF16x3 fast product (the same split, exact products)
+    stays under the gate against the exact product, and within 40x of it, so
+    the gate describes the error rather than being vacuous."""
+    import fmm_inputs
+    from oracle import bf16x3
+    a = algorithms.get(name)
+    m, k, n = a.M ** L * 20 + 3, a.K ** L * 30 + 1, a.N ** L * 20 + 2
+    A, B = fmm_inputs.operands(7, m, k, n, kind, np.float32)
+    ref = classical.gemm(A, B)
+    err = np.linalg.norm(bf16x3.fmm(a, L, A, B) - ref) / np.linalg.norm(ref)
+    g = bf16x3.gate(a, L, k)
+    assert g / 40 <= err <= g, (err, g)
+
+
+@pytest.mark.parametrize("name", ALGS)
+def test_bf16x3_gate_catches_a_dropped_cross_term(name, monkeypatch):
+    """Planted mistake in the emulation: leaves without the lo*hi term.  The
+    error then exceeds the gate, so a kernel that lost a product term would
+    fail the GPU gate against the binary64 oracle."""
+    import fmm_inputs
+    from oracle import bf16x3
+
+    def two_terms(A, B):
+        ah, al = bf16x3.split(A)
+        bh, bl = bf16x3.split(B)
+        ah, bh, bl = (v.astype(np.float64) for v in (ah, bh, bl))
+        return ah @ bh + ah @ bl
+
+    monkeypatch.setattr(bf16x3, "gemm", two_terms)
+    a = algorithms.get(name)
+    m, k, n = a.M * 20 + 3, a.K * 30 + 1, a.N * 20 + 2
+    A, B = fmm_inputs.operands(8, m, k, n, "uniform", np.float32)
+    ref = classical.gemm(A, B)
+    err = np.linalg.norm(bf16x3.fmm(a, 1, A, B) - ref) / np.linalg.norm(ref)
+    assert err > 4 * bf16x3.gate(a, 1, k), (err, bf16x3.gate(a, 1, k))

@@ -42,9 +42,13 @@ def test_budget_prunes_by_workspace():
 
 
 def test_restricted_to_one_base_case():
-    c = F.rank_candidates(8192, 8192, 8192, F.F32, alg="strassen_222_7")
+    c = F.rank_candidates(8192, 8192, 8192, F.F32, alg="strassen_222_7", max_error=-1)
     assert {x["alg"] for x in c} == {"strassen_222_7"}
     assert sorted(x["levels"] for x in c) == [0, 1, 2, 3, 4, 5]
+    # the default FP32 error budget (1e-4) stops at four levels: the bound
+    # (2 + sqrt(8192)) 2^-24 2^L is 8.8e-5 at L = 4 and 1.8e-4 at L = 5
+    c = F.rank_candidates(8192, 8192, 8192, F.F32, alg="strassen_222_7")
+    assert sorted(x["levels"] for x in c) == [0, 1, 2, 3, 4]
     # leaf dimensions stay >= 64: 256 / 2^2 = 64, the third level is not offered;
     # depth 0 (the classical product) is always a candidate
     c = F.rank_candidates(256, 256, 256, F.F64, alg="strassen_222_7")
@@ -145,21 +149,22 @@ def test_model_summary_equals_the_full_plan(fuse, dtype, monkeypatch):
     checked = 0
     for shape in shapes:
         for alg in ["strassen_222_7", "fmm_333_23", "fmm_323_15", "fmm_423_20", "fmm_424_26"]:
-            for c in F.rank_candidates(*shape, dtype, alg=alg, budget_bytes=1 << 50):
+            for c in F.rank_candidates(*shape, dtype, alg=alg, budget_bytes=1 << 50, max_error=-1):
                 p = F.Plan(c["alg"], *shape, c["levels"], dtype=dtype, host_only=True)
                 i = p.info
                 assert c["workspace_bytes"] == i["workspace_bytes"], (shape, c)
                 assert abs(c["add_ms"] - i["add_bytes"] / 4.8e12 * 1e3) <= 1e-12 * max(1.0, c["add_ms"])
                 checked += 1
         # one base case per level (two-level mixes from the model, and longer lists)
-        mixed = [c for c in F.rank_candidates(*shape, dtype, budget_bytes=1 << 50) if "+" in c["alg"]]
+        mixed = [c for c in F.rank_candidates(*shape, dtype, budget_bytes=1 << 50, max_error=-1)
+                 if "+" in c["alg"]]
         lists = [("fmm_333_23+strassen_222_7+fmm_424_26", 3), ("strassen_222_7+strassen_222_7+fmm_323_15", 3)]
         for alg, L in [(c["alg"], c["levels"]) for c in mixed] + lists:
             try:
                 p = F.Plan(alg, *shape, L, dtype=dtype, host_only=True)
             except F.FmmError:
                 continue  # a leaf dimension < 1
-            c = F.rank_candidates(*shape, dtype, alg=alg, budget_bytes=1 << 50)[0]
+            c = F.rank_candidates(*shape, dtype, alg=alg, budget_bytes=1 << 50, max_error=-1)[0]
             i = p.info
             assert (c["alg"], c["levels"]) == (alg, L)
             assert c["workspace_bytes"] == i["workspace_bytes"], (shape, alg)
@@ -214,3 +219,67 @@ def test_concurrent_planning_and_ranking_agree_with_serial():
             assert top == picked and rec == ("strassen_222_7", 1)
     finally:
         autotune.clear()
+
+
+def test_error_budget_limits_the_automatic_choice():
+    """The automatic choice honours a per-dtype error budget: at 16384^3 on
+    the BF16x3 path <4,2,4> at two levels (bound 1.7e-3) is not offered under
+    the default 5e-4, and is with no limit; every offered candidate is within
+    the budget, and an "auto" plan's bound is too."""
+    shape = (16384, 16384, 16384)
+    c = F.rank_candidates(*shape, F.F32_BF16X3)
+    assert c and all(x["error_bound"] <= 5e-4 for x in c)
+    assert ("fmm_424_26", 2) not in {(x["alg"], x["levels"]) for x in c}
+    free = F.rank_candidates(*shape, F.F32_BF16X3, max_error=-1)
+    assert ("fmm_424_26", 2) in {(x["alg"], x["levels"]) for x in free}
+    p = F.Plan("auto", *shape, -1, dtype=F.F32_BF16X3, host_only=True)
+    assert p.info["error_bound"] <= 5e-4
+    tight = F.Plan("auto", *shape, -1, dtype=F.F32_BF16X3, host_only=True, max_error=1e-4)
+    assert tight.info["error_bound"] <= 1e-4
+    # FP64: the benchmark's <4,2,4> at two levels is within the 1e-12 default
+    p = F.Plan("auto", *shape, -1, dtype=F.F64, host_only=True)
+    assert (p.alg, p.levels) == ("fmm_424_26", 2) and p.info["error_bound"] <= 1e-12
+    # a named plan is not limited
+    named = F.Plan("fmm_424_26", *shape, 2, dtype=F.F32_BF16X3, host_only=True)
+    assert named.info["error_bound"] > 5e-4
+
+
+def test_recorded_choice_above_the_error_budget_is_ignored():
+    from paper_1409_2908_amd import autotune
+    shape = (8192, 8192, 8192)
+    try:
+        autotune.record(*shape, F.F32_BF16X3, "fmm_424_26", 2)
+        p = F.Plan("auto", *shape, -1, dtype=F.F32_BF16X3, host_only=True)
+        assert (p.alg, p.levels) != ("fmm_424_26", 2) and p.info["error_bound"] <= 5e-4
+        loose = F.Plan("auto", *shape, -1, dtype=F.F32_BF16X3, host_only=True, max_error=-1)
+        assert (loose.alg, loose.levels) == ("fmm_424_26", 2)
+    finally:
+        autotune.clear()
+
+
+@pytest.mark.parametrize("name", ["strassen_222_7", "fmm_333_23", "fmm_323_15", "fmm_423_20", "fmm_424_26"])
+def test_error_bound_equals_the_oracle_gate(name):
+    """The library's error bound (from its own tables) and the oracle's
+    BF16x3 gate (from the oracle's tables) are the same formula computed
+    independently; they agree for every base case and depth."""
+    from oracle import algorithms, bf16x3
+    a = algorithms.get(name)
+    for L in (0, 1, 2, 3):
+        m, k, n = a.M ** L * 70, a.K ** L * 90 + 3, a.N ** L * 70
+        p = F.Plan(name, m, k, n, L, dtype=F.F32_BF16X3, host_only=True)
+        assert p.info["error_bound"] == pytest.approx(bf16x3.gate(a, L, k), rel=1e-12), (name, L)
+    mixed = F.Plan("strassen_222_7+" + name, 640, 640, 640, 2, dtype=F.F32_BF16X3, host_only=True)
+    assert mixed.info["error_bound"] == pytest.approx(
+        bf16x3.gate([algorithms.get("strassen_222_7"), a], 2, 640), rel=1e-12)
+
+
+def test_pair_formed_plans_count_one_formation_launch():
+    """One-level FP64 plans with few positions form S and T in one launch;
+    the model then counts three launches (formation, leaves, combination)."""
+    p = F.Plan("strassen_222_7", 512, 512, 512, 1, host_only=True)
+    assert p.info["pair_form"] == 1
+    c = F.rank_candidates(512, 512, 512, F.F64, alg="strassen_222_7")
+    one = [x for x in c if x["levels"] == 1][0]
+    assert one["model_ms"] - one["leaf_ms"] - one["add_ms"] == pytest.approx(3 * 6e-3, rel=1e-9)
+    assert F.Plan("strassen_222_7", 512, 512, 512, 1, dtype=F.F32_BF16X3, host_only=True).info["pair_form"] == 0
+    assert F.Plan("strassen_222_7", 4096, 4096, 4096, 1, host_only=True).info["pair_form"] == 0
