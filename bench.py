@@ -215,9 +215,17 @@ def main():
     elif dt == F.F32:
         kernel, peak, tag = f"gemm_kernel<float, {tile}, {tile}>", FP32_PEAK_TFLOPS, f"gemm_f32_t{tile}"
     else:
-        # three bf16 products per FP32 product, priced at the bf16 matrix peak
-        tile = 64 if t128 < cus else 128
-        kernel, peak, tag = f"gemm_bf16x3_kernel<{tile}>", BF16_PEAK_TFLOPS, f"gemm_bf16x3_t{tile}"
+        # three bf16 products per FP32 product, priced at the bf16 matrix peak;
+        # the library's per-launch rule: split leaf operands with whole
+        # k-octets run 256 x 256 tiles when there are two per compute unit
+        leaf_k_octets = info["leaf_k"] % 8 == 0 and info["levels"] > 0
+        t256 = -(-info["leaf_m"] // 256) * -(-info["leaf_n"] // 256) * info["num_leaves"]
+        if leaf_k_octets and t256 >= 2 * cus:
+            kernel, tag = "gemm_bf16x3_big_kernel", "gemm_bf16x3_t256"
+        else:
+            tile = 64 if t128 < cus else 128
+            kernel, tag = f"gemm_bf16x3_kernel<{tile}>", f"gemm_bf16x3_t{tile}"
+        peak = BF16_PEAK_TFLOPS
         leaf_tflops *= 3
     traffic = traffic_from_profile(tag)
     workload = (f"FP64 square {m}x{k}x{n}, uniform[-1,1)" if dt == F.F64 else

@@ -114,10 +114,13 @@ typedef struct {
                           stage timing is on. */
     int defer_device_memory; /* non-zero: allocate nothing on the device; the caller binds
                           fmm_plan_device_bytes(p) bytes with fmm_plan_bind before running */
-    int leaf_tile;     /* output tile edge of the FP64 / FP32 leaf GEMM: 128 or 64; 0 (default):
-                          chosen per launch, 64 when the launch has fewer 128 x 128 tiles than
-                          the device has compute units.  BF16x3 leaves always use 128.  Other
-                          values: FMM_EINVAL.  Batched launches always choose per launch. */
+    int leaf_tile;     /* output tile edge of the leaf GEMM: 128 or 64 (FP64 / FP32 / BF16x3), or
+                          256 (BF16x3 leaves with split operands; peel strips then take 128);
+                          0 (default): chosen per launch -- BF16x3 leaves 256 when the launch has
+                          at least two 256 x 256 tiles per compute unit, otherwise 64 when the
+                          launch has fewer 128 x 128 tiles than the device has compute units,
+                          else 128.  Every tile edge gives the same bits.  Other values:
+                          FMM_EINVAL.  Batched launches always choose per launch. */
     double max_error;  /* automatic choice only (alg "auto" or levels -1): the largest
                           error_bound (fmm_plan_info_t) a chosen plan may have; 0: the dtype's
                           default (1e-12 FP64, 1e-4 FP32, 5e-4 BF16x3); < 0: no limit.

@@ -311,7 +311,8 @@ fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
                        int leaf_tile = 0, double max_error = 0) {
   if (!out) return fail(FMM_EINVAL, "out is NULL");
   *out = nullptr;
-  if (leaf_tile != 0 && leaf_tile != 64 && leaf_tile != 128) return fail(FMM_EINVAL, "leaf_tile must be 0, 64 or 128");
+  if (leaf_tile != 0 && leaf_tile != 64 && leaf_tile != 128 && !(leaf_tile == 256 && dtype == FMM_F32_BF16X3))
+    return fail(FMM_EINVAL, "leaf_tile must be 0, 64 or 128 (or 256 on the BF16x3 path)");
   fmm_status st = check_tables_once();
   if (st != FMM_OK) return st;
   if (dtype == FMM_F32_BF16X3 && !fmm::kHaveBf16x3)
@@ -844,7 +845,8 @@ fmm_status fmm_tune_record(int64_t m, int64_t k, int64_t n, int dtype, const cha
     if (pr > 0) return fail((fmm_status)pr, err);
   }
   if (levels < 0 || fuse_levels < 0 || fuse_levels > 2) return fail(FMM_EINVAL, "bad levels or fuse_levels");
-  if (leaf_tile != 0 && leaf_tile != 64 && leaf_tile != 128) return fail(FMM_EINVAL, "leaf_tile must be 0, 64 or 128");
+  if (leaf_tile != 0 && leaf_tile != 64 && leaf_tile != 128 && !(leaf_tile == 256 && dtype == FMM_F32_BF16X3))
+    return fail(FMM_EINVAL, "leaf_tile must be 0, 64 or 128 (or 256 on the BF16x3 path)");
   fmm::Plan P;
   int code = 0;
   std::string err = fmm::make_plan(P, alg, m, k, n, levels, dtype, fuse_levels, &code);

@@ -543,6 +543,195 @@ __device__ __forceinline__ void bf16x3_tile64(Bf16x3Smem64& sm, const float* A, 
   bf16x3_mma64(sm, gload, lstore, C, ldc, mrem, nrem, K, alpha);
 }
 
+// 256 x 256 tiles (launches with many tiles): one workgroup of 4 wavefronts
+// per compute unit, each wavefront 128 x 128 outputs (8 x 8 blocks of
+// v_mfma_f32_16x16x32_bf16).  Per K step of 32 a wavefront reads 32 KB of
+// fragments from LDS for 192 MFMAs, half the LDS bytes per MFMA of the
+// 64 x 64 wavefront tile, and the workgroup writes 64 KB of staged operands for
+// 4x the MFMAs of a 128 x 128 workgroup tile: the LDS traffic drops from about
+// the whole LDS bandwidth at full matrix-core rate to about half of it.  Every
+// output accumulates the same three MFMAs per K step of 32 in the same order
+// as the 64 x 64 and 128 x 128 tiles, so all tile shapes agree bit for bit.
+// LDS holds 16-byte k groups (8 bf16: one fragment's worth), 4 per row and
+// K step, at slot g ^ ((r >> 1) & 3) of their row so that the 8 rows 8
+// consecutive lanes read together land in 8 distinct 16-byte slots of a
+// 128-byte line; two buffers of 64 KB (A and B, hi and lo planes).
+constexpr int ZBM = 256;
+
+struct Bf16x3SmemBig {
+  u4_t a[2][2][ZBM * 4];  // [buffer][plane][row * 4 + slot]
+  u4_t b[2][2][ZBM * 4];  // [buffer][plane][column * 4 + slot]
+};
+static_assert(sizeof(Bf16x3SmemBig) == 128 * 1024, "LDS layout of the 256 x 256 tile");
+
+__device__ __forceinline__ int zslot(int r, int g) { return r * 4 + (g ^ ((r >> 1) & 3)); }
+
+// One 256 x 256 output tile of a leaf with split operands (layouts as
+// bf16x3_tile_split: S planes row-major, T planes in k-octets) and K a
+// multiple of 8.  Operands go from memory to LDS by direct loads
+// (buffer_load_dwordx4 ... lds): each instruction moves 64 16-byte groups and
+// lane i lands at byte 16 i of its wave's 1 KB LDS chunk, so a chunk is 16
+// rows (or columns) x 4 slots and lane i fetches the k group that the swizzle
+// puts in its slot; lanes past the tile edge or past K read through an
+// out-of-range offset and write zeros.  No registers hold staged data and no
+// LDS store instructions are issued.
+__device__ __forceinline__ void bf16x3_tile_split256(Bf16x3SmemBig& sm, const __bf16* Ah, const __bf16* Al,
+                                                     const __bf16* Bh, const __bf16* Bl, float* C, int lda,
+                                                     int ldb, int ldc, int mrem, int nrem, int K, float alpha) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, lg = lane >> 4;
+
+  // direct-load lanes: wave w fills chunks 4 w .. 4 w + 3 of each plane;
+  // lane i covers row / column 64 w + 16 q + i / 4 of chunk q and the k
+  // group g = (i & 3) ^ ((i >> 3) & 3) (the swizzle of that row)
+  const int dr = wave * 64 + (lane >> 2);
+  const int dg = (lane & 3) ^ ((lane >> 3) & 3);
+  const int a_lane = (dr * lda + 8 * dg) * 2;
+  const int a_q = uniform_int(16 * lda * 2);
+  const int b_lane = (dg * ldb + 8 * dr) * 2;
+  bool a_ok[4], b_ok[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    a_ok[q] = dr + 16 * q < mrem;
+    b_ok[q] = dr + 16 * q < nrem;
+  }
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  // plane p of A (side 0) or B (side 1), chunks of wave `wave`, step k0
+  auto dma = [&](int side, int p, int buf, int k0) {
+    const bool kv = k0 + 8 * dg < K;
+    if (side == 0) {
+      const __amdgpu_buffer_rsrc_t r = make_rsrc((p ? Al : Ah) + k0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)&sm.a[buf][p][(wave * 4 + q) * 64], 16,
+                                                 (a_ok[q] && kv) ? a_lane : kInvalidOff, q * a_q, 0, 0);
+    } else {
+      const __amdgpu_buffer_rsrc_t r = make_rsrc((p ? Bl : Bh) + (int64_t)(k0 >> 3) * ldb);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)&sm.b[buf][p][(wave * 4 + q) * 64], 16,
+                                                 (b_ok[q] && kv) ? b_lane : kInvalidOff, q * 256, 0, 0);
+    }
+  };
+
+  f4_t acc[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
+
+  const int nk = (K + XBK - 1) / XBK;
+  // Fragments: A (hi, lo) of all 8 row blocks of the step, B (hi, lo) of the
+  // column block in use and of the next one.  One barrier per K step, after
+  // the seventh column block: every read of the current buffer is issued
+  // before it, and the direct loads of the next step (issued over the first
+  // four column blocks) have landed in the other buffer; after it the next
+  // step's fragments are read while the last column block's MFMAs run, each A
+  // fragment replaced right after its last use.  The loop body has no
+  // branches: the last step also loads and reads a step past K (out-of-range
+  // loads write zeros; nothing uses those values).
+  bf8_t ah[8], al[8], bh[2], bl[2];
+  auto frag = [&](const u4_t* plane, int r) { return __builtin_bit_cast(bf8_t, plane[zslot(r, lg)]); };
+  auto rd_b = [&](int buf, int j) {
+    bh[j & 1] = frag(sm.b[buf][0], wn * 128 + j * 16 + li);
+    bl[j & 1] = frag(sm.b[buf][1], wn * 128 + j * 16 + li);
+  };
+  auto mma = [&](int j) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j & 1], acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j & 1], acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j & 1], acc[i][j], 0, 0, 0);
+    }
+  };
+  // vmcnt(0) only (expcnt and lgkmcnt at their maxima): the direct loads
+  // count as vector-memory loads until their data is in LDS
+  constexpr int kWaitVm0 = 0x0F70;
+  dma(0, 0, 0, 0);
+  dma(0, 1, 0, 0);
+  dma(1, 0, 0, 0);
+  dma(1, 1, 0, 0);
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    ah[i] = frag(sm.a[0][0], wm * 128 + i * 16 + li);
+    al[i] = frag(sm.a[0][1], wm * 128 + i * 16 + li);
+  }
+  rd_b(0, 0);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1, nxt = cur ^ 1;
+    const int k1 = (kt + 1) * XBK;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+      if (j < 4) dma(j >> 1, j & 1, nxt, k1);
+      rd_b(cur, j + 1);
+      mma(j);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    __syncthreads();
+    // last column block: once a row block's three MFMAs are issued, its A
+    // fragments are replaced by the next step's
+    const bf8_t bh7 = bh[1], bl7 = bl[1];
+    rd_b(nxt, 0);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      acc[i][7] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh7, acc[i][7], 0, 0, 0);
+      acc[i][7] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl7, acc[i][7], 0, 0, 0);
+      acc[i][7] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh7, acc[i][7], 0, 0, 0);
+      ah[i] = frag(sm.a[nxt][0], wm * 128 + i * 16 + li);
+      al[i] = frag(sm.a[nxt][1], wm * 128 + i * 16 + li);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+
+  const __amdgpu_buffer_rsrc_t sc = make_rsrc(C);
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wm * 128 + i * 16 + 4 * lg + v;
+        const int c = wn * 128 + j * 16 + li;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, alpha * acc[i][j][v]), sc,
+                                              (r < mrem && c < nrem) ? (r * ldc + c) * 4 : kInvalidOff, 0, 0);
+      }
+  // the next tile's first loads write buffer 0, which other wavefronts may
+  // still be reading (the reads after the last step)
+  __syncthreads();
+}
+
+// Grouped launch on 256 x 256 tiles of problems with split operands and K a
+// multiple of 8 (the launcher gives it only such groups).
+__global__ void __launch_bounds__(XNT) __attribute__((amdgpu_waves_per_eu(1, 1)))
+gemm_bf16x3_big_kernel(GemmArgs args) {
+  const GemmArgs* ap = kernarg_args();
+  __shared__ Bf16x3SmemBig sm;
+  const int64_t G = gridDim.x;
+  const int64_t slot = (int64_t)(blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
+  for (int64_t t = slot; t < ap->total_tiles; t += G) {
+    const TileJob job = decode_tile(ap, t);
+    const GemmProb pr = job.probs ? job.probs[job.prob] : ap->single;
+    int64_t lda, ldb, ldc;
+    const char* abase = slot_ptr(ap, job.slot, pr.a, &lda);
+    const char* bbase = slot_ptr(ap, job.slot, pr.b, &ldb);
+    float* C = (float*)slot_ptr(ap, job.slot, pr.c, &ldc) + pr.c.off;
+    C = uniform_ptr(C + (pr.c.row + job.tm * ZBM) * ldc + pr.c.col + job.tn * ZBM);
+    const int64_t mr = job.m - job.tm * ZBM, nr = job.n - job.tn * ZBM;
+    const int mrem = uniform_int(mr < ZBM ? (int)mr : ZBM);
+    const int nrem = uniform_int(nr < ZBM ? (int)nr : ZBM);
+    const __bf16* Ah = uniform_ptr((const __bf16*)abase + pr.a.off + job.tm * ZBM * lda);
+    const __bf16* Bh = uniform_ptr((const __bf16*)bbase + pr.b.off + job.tn * ZBM * 8);
+    bf16x3_tile_split256(sm, Ah, uniform_ptr(Ah + pr.a.plane), Bh, uniform_ptr(Bh + pr.b.plane), C,
+                         uniform_int((int)lda), uniform_int((int)ldb), uniform_int((int)ldc), mrem, nrem,
+                         uniform_int((int)job.k), (float)uniform_double(pr.alpha));
+  }
+}
+
 template <int TM>
 __global__ void __launch_bounds__(XNT) __attribute__((amdgpu_waves_per_eu(2, TM == 128 ? 2 : 4)))
 gemm_bf16x3_kernel(GemmArgs args) {
@@ -629,10 +818,81 @@ static hipError_t launch_bf16x3_tiles(const GemmArgs& a, int num_cus, hipStream_
   return hipGetLastError();
 }
 
-// Tile edge: an explicit 64 or 128 wins, otherwise 64 when the launch has
-// fewer 128 x 128 tiles than compute units (use_small_tiles).
+// Re-counts the flat tile space of `a` for TM x TM tiles.
+static GemmArgs retile(const GemmArgs& a, int tm) {
+  GemmArgs re = a;
+  int64_t tiles = 0;
+  for (int i = 0; i < re.ngroups; ++i) {
+    GemmGroup& g = re.groups[i];
+    g.tiles_m = (g.m + tm - 1) / tm;
+    g.tiles_n = (g.n + tm - 1) / tm;
+    g.tile_start = tiles;
+    tiles += g.tiles_m * g.tiles_n * g.count;
+  }
+  re.total_tiles = tiles;
+  return re;
+}
+
+static hipError_t launch_bf16x3_big(const GemmArgs& a, int num_cus, hipStream_t s) {
+  const GemmArgs re = retile(a, ZBM);
+  static std::atomic<int> cached{0};
+  int per_cu = cached.load(std::memory_order_relaxed);
+  if (!per_cu) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gemm_bf16x3_big_kernel, XNT, 0) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    cached.store(per_cu, std::memory_order_relaxed);
+  }
+  int64_t G = (int64_t)per_cu * num_cus;
+  const int64_t want = (re.total_tiles + 7) / 8 * 8;
+  if (want < G) G = want;
+  if (G < 8) G = 8;
+  G = G / 8 * 8;
+  hipLaunchKernelGGL(gemm_bf16x3_big_kernel, dim3((unsigned)G), dim3(XNT), 0, s, re);
+  return hipGetLastError();
+}
+
+// Groups the 256 x 256 kernel takes: split operands and K a multiple of 8
+// (whole k-octets, which its direct loads need: a partial octet's padding
+// would have to be zeroed in registers).
+static bool big_group(const GemmGroup& g) { return g.split && g.k % 8 == 0; }
+
+// Number of 256 x 256 tiles of the groups the big kernel takes.
+static int64_t split_tiles256(const GemmArgs& a) {
+  int64_t t = 0;
+  for (int i = 0; i < a.ngroups; ++i) {
+    const GemmGroup& g = a.groups[i];
+    if (big_group(g)) t += ((g.m + ZBM - 1) / ZBM) * ((g.n + ZBM - 1) / ZBM) * g.count;
+  }
+  return t;
+}
+
+// The groups of `a` the big kernel takes (big) or not, tile counts for 128 x 128.
+static GemmArgs select_groups(const GemmArgs& a, bool big) {
+  GemmArgs re = a;
+  re.ngroups = 0;
+  for (int i = 0; i < a.ngroups; ++i)
+    if (big_group(a.groups[i]) == big) re.groups[re.ngroups++] = a.groups[i];
+  return retile(re, XBM);
+}
+
+// Tile edge: an explicit 64, 128 or 256 wins (256 for split-operand groups
+// only); otherwise the split-operand groups run 256 x 256 tiles when they
+// have at least two per compute unit, and the rest (or everything) 64 x 64
+// tiles when the launch has fewer 128 x 128 tiles than compute units
+// (use_small_tiles), else 128 x 128.  The big tiles take a launch of their
+// own, so a plan with peel strips then makes two launches.
 hipError_t launch_gemm_bf16x3(const GemmArgs& a, int num_cus, hipStream_t s) {
   if (a.total_tiles <= 0) return hipSuccess;
+  const int64_t big = split_tiles256(a);
+  if (big > 0 && (a.tile == 256 || (a.tile == 0 && big >= 2 * (int64_t)num_cus))) {
+    hipError_t e = launch_bf16x3_big(select_groups(a, true), num_cus, s);
+    if (e != hipSuccess) return e;
+    const GemmArgs rest = select_groups(a, false);
+    if (rest.total_tiles <= 0) return hipSuccess;
+    const bool small = use_small_tiles(rest.total_tiles, num_cus, true);
+    return small ? launch_bf16x3_tiles<64>(rest, num_cus, s) : launch_bf16x3_tiles<128>(rest, num_cus, s);
+  }
   const bool small = a.tile == 64 || (a.tile != 128 && use_small_tiles(a.total_tiles, num_cus, true));
   return small ? launch_bf16x3_tiles<64>(a, num_cus, s) : launch_bf16x3_tiles<128>(a, num_cus, s);
 }

@@ -101,7 +101,7 @@ struct GemmGroup {
   int64_t prob_start;  // index of the group's first problem in `probs`
   const GemmProb* probs = nullptr;  // device array; NULL means GemmArgs::single
   int32_t slot = 0;                 // index into GemmArgs::bases
-  int32_t pad = 0;
+  int32_t split = 0;                // 1: every problem's operands are split planes (ELT_BF16X2)
 };
 
 constexpr int kMaxGemmGroups = 24;  // groups per launch (a plan has at most 4)

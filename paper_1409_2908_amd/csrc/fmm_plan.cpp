@@ -318,6 +318,7 @@ std::string summarize_plan(PlanSummary& S, const char* alg, int64_t m, int64_t k
     const int64_t m_stride = round_up(ml * m_ld * (int64_t)es, 256) / (int64_t)es;
     ws.alloc_many(1, (size_t)m_stride * es * nleaves);
     S.groups.push_back(GemmGroup{ml, nl, kl, nleaves, 0, 0, 0, 0});
+    S.groups.back().split = dtype == 2 ? 1 : 0;
     const bool has_p = k0 < k;
     if (has_p) {
       ws.alloc_many(1, (size_t)m0 * round_up(n0, 16) * es);
@@ -479,6 +480,7 @@ std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n,
     const int64_t m_stride = round_up(P.ml * m_ld * (int64_t)es, 256) / (int64_t)es;
     const size_t m_base = ws.alloc((size_t)m_stride * es * nleaves);
     GemmGroup g0{P.ml, P.nl, P.kl, nleaves, 0, 0, 0, 0};
+    g0.split = S[0].elt == ELT_BF16X2 ? 1 : 0;  // BF16x3 leaves read split operands, never views
     P.gemm_groups.push_back(g0);
     for (int64_t r = 0; r < nleaves; ++r) {
       GemmProb pr{};

@@ -35,6 +35,7 @@ constexpr double kRateF64 = 65e12;          // flop/s, FP64 MFMA
 constexpr double kRateF32 = 110e12;         // flop/s, FP32 MFMA
 constexpr double kRateBf16x3Split = 300e12; // FP32-equivalent flop/s, BF16x3 on split leaf operands
 constexpr double kRateBf16x3 = 245e12;      // FP32-equivalent flop/s, BF16x3 splitting FP32 tiles
+constexpr double kRateBf16x3Big = 430e12;   // FP32-equivalent flop/s, BF16x3 256 x 256 tiles (split operands)
 constexpr double kAddBw = 4.8e12;           // byte/s, formation / combination passes
 constexpr double kLaunch = 6e-6;       // s per kernel launch on a busy stream
 constexpr double kFix = 32;            // per-tile fixed cost, in units of k
@@ -75,7 +76,30 @@ void predict(const PlanSummary& P, int dtype, Candidate& c) {
     return std::ceil(u / (slots * w)) * w * 2.0 * tile_edge * tile_edge / (r / slots);
   };
   double leaf_s = 0;
-  if (tiles > 0 && use_small_tiles((int64_t)tiles, kCUs, dtype == 2)) {
+  // BF16x3: split-operand groups with whole k-octets run 256 x 256 tiles,
+  // one workgroup per compute unit, when they have two such tiles per CU;
+  // the other groups then take a launch of 128 x 128 tiles of their own
+  double big_tiles = 0, big_units = 0, big_w = 0;
+  if (dtype == 2)
+    for (const GemmGroup& g : P.groups)
+      if (g.split && g.k % 8 == 0) {
+        const double t = (double)((g.m + 255) / 256) * ((g.n + 255) / 256) * g.count;
+        big_tiles += t;
+        big_units += t * ((double)g.k + kFix);
+        big_w = std::max(big_w, (double)g.k + kFix);
+      }
+  if (big_tiles >= 2.0 * kCUs) {
+    leaf_s = waves_time(big_units, big_w, big_tiles, 1, 256, kRateBf16x3Big);
+    double units_r = 0, w_r = 0, tiles_r = 0;
+    for (const GemmGroup& g : P.groups)
+      if (!(g.split && g.k % 8 == 0)) {
+        const double t = (double)g.tiles_m * g.tiles_n * g.count;
+        units_r += t * ((double)g.k + kFix);
+        tiles_r += t;
+        w_r = std::max(w_r, (double)g.k + kFix);
+      }
+    if (tiles_r > 0) leaf_s += waves_time(units_r, w_r, tiles_r, kSlots / kCUs, (double)kTileM, kRateBf16x3) + kLaunch;
+  } else if (tiles > 0 && use_small_tiles((int64_t)tiles, kCUs, dtype == 2)) {
     // the launch runs 64 x 64 tiles (units weighted by each group's rate,
     // as for the large tiles)
     double units64 = 0, tiles64 = 0;

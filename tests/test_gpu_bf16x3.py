@@ -187,26 +187,28 @@ def test_fp32_fused_levels_bitwise_equal_unfused(F, alg, L, dtype_name, monkeypa
 
 @pytest.mark.parametrize("alg,L,shape", [("classical", 0, (300, 211, 515)), ("classical", 0, (65, 1001, 130)),
                                          ("strassen_222_7", 1, (517, 262, 383)),
-                                         ("fmm_424_26", 1, (1030, 778, 1029))])
+                                         ("fmm_424_26", 1, (1030, 778, 1029)),
+                                         ("strassen_222_7", 1, (1030, 778, 1029)),
+                                         ("strassen_222_7", 2, (2063, 1001, 2050))])
 def test_bf16x3_leaf_tile_shapes_agree(F, alg, L, shape):
-    """64 x 64 and 128 x 128 BF16x3 tiles run the same three MFMA products
-    over the same K steps, so they agree bit for bit (split leaf operands and
-    FP32 operands split while staged); both match the emulation."""
+    """64 x 64, 128 x 128 and (split leaf operands) 256 x 256 BF16x3 tiles
+    run the same three MFMA products over the same K steps, so they agree bit
+    for bit (split leaf operands and FP32 operands split while staged, ragged
+    tile edges, a partial last K step, peel strips); all match the emulation."""
     m, k, n = shape
     say(f"case bf16x3 leaf tiles {alg} L={L} {m}x{k}x{n}")
     A, B = fmm_inputs.operands(19, m, k, n, "normal_rowscaled", np.float32)
     out = {}
-    for tile in (64, 128, 0):
+    for tile in (64, 128, 256, 0):
         with F.Plan(alg, m, k, n, L, F.F32_BF16X3, leaf_tile=tile) as p:
             out[tile] = to_host(p.multiply(to_dev(A), to_dev(B)))
     a = None if alg == "classical" else algorithms.get(alg)
     emu = bf16x3.gemm(A, B) if a is None else bf16x3.fmm(a, L, A, B)
-    for tile in (64, 128):
+    for tile in (64, 128, 256):
         assert relf(out[tile], emu) <= 2e-6 * 2 ** max(L, 1), tile
+        assert np.array_equal(out[tile].view(np.int32), out[64].view(np.int32)), tile
     assert relf(out[0], classical.gemm(A, B)) <= bf16x3.gate(a, L, k) if a else 2e-5
-    assert np.array_equal(out[64].view(np.int32), out[128].view(np.int32))
     assert np.array_equal(out[0].view(np.int32), out[64].view(np.int32))
-
 
 
 @pytest.mark.parametrize("spec,names", [("fmm_424_26+strassen_222_7", ["fmm_424_26", "strassen_222_7"]),
