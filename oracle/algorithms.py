@@ -14,6 +14,8 @@ import re
 from dataclasses import dataclass
 from typing import List
 
+from . import tensor
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
 
@@ -149,6 +151,85 @@ def load_table(path, name=None):
     return Algorithm(nm, M, K, N, R, U, V, W)
 
 
+def classical(M, K, N):
+    """The classical <M,K,N;MKN> scheme written as a bilinear algorithm:
+    product (a, b, c) multiplies A_ab by B_bc and goes to C_ac."""
+    R = M * K * N
+    U = [[0] * R for _ in range(M * K)]
+    V = [[0] * R for _ in range(K * N)]
+    W = [[0] * R for _ in range(M * N)]
+    r = 0
+    for a in range(M):
+        for b in range(K):
+            for c in range(N):
+                U[a * K + b][r] = 1
+                V[b * N + c][r] = 1
+                W[a * N + c][r] = 1
+                r += 1
+    return Algorithm(f"classical_{M}{K}{N}_{R}", M, K, N, R, tuple(map(tuple, U)),
+                     tuple(map(tuple, V)), tuple(map(tuple, W)))
+
+
+def permuted(alg, dims, name=None):
+    """An algorithm for `dims` obtained from `alg` by Propositions 2.1 and 2.2
+    (Section 2.3): the first sequence of them, by length and with 2.1 before
+    2.2 at each position, whose result has the wanted dimensions."""
+    from itertools import product
+    for length in range(4):
+        for seq in product((1, 2), repeat=length):
+            U, V, W, d = alg.U, alg.V, alg.W, alg.dims
+            for prop in seq:
+                fn = tensor.prop21 if prop == 1 else tensor.prop22
+                U, V, W, d = fn(U, V, W, *d)
+            if tuple(d) == tuple(dims):
+                return Algorithm(name or alg.name, d[0], d[1], d[2], alg.R, tuple(map(tuple, U)),
+                                 tuple(map(tuple, V)), tuple(map(tuple, W)))
+    raise ValueError(dims)
+
+
+def direct_sum_n(algs, name):
+    """The direct sum along N of algorithms for <M,K,N_1>, <M,K,N_2>, ...:
+    B and C are split into column blocks of N_1, N_2, ... block columns and
+    each part is multiplied by its own algorithm; the products of the first
+    algorithm come first."""
+    M, K = algs[0].M, algs[0].K
+    N = sum(a.N for a in algs)
+    R = sum(a.R for a in algs)
+    U = [[] for _ in range(M * K)]
+    V = [[0] * R for _ in range(K * N)]
+    W = [[0] * R for _ in range(M * N)]
+    r0 = c0 = 0
+    for a in algs:
+        assert (a.M, a.K) == (M, K)
+        for i in range(M * K):
+            U[i] += list(a.U[i])
+        for r in range(a.R):
+            for b in range(K):
+                for c in range(a.N):
+                    V[b * N + c0 + c][r0 + r] = a.V[b * a.N + c][r]
+            for x in range(M):
+                for c in range(a.N):
+                    W[x * N + c0 + c][r0 + r] = a.W[x * a.N + c][r]
+        r0 += a.R
+        c0 += a.N
+    return Algorithm(name, M, K, N, R, tuple(map(tuple, U)), tuple(map(tuple, V)), tuple(map(tuple, W)))
+
+
+def _dims(name):
+    d = name.split("_")[1]
+    return int(d[0]), int(d[1]), int(d[2])
+
+
+# Permutations (Propositions 2.1 / 2.2) and direct sums of the base tables
+# that give the other shapes of Table 2's ranks.
+_PERMUTED = {"fmm_332_15": "fmm_323_15", "fmm_233_15": "fmm_323_15",
+             "fmm_324_20": "fmm_423_20", "fmm_342_20": "fmm_423_20", "fmm_243_20": "fmm_423_20",
+             "fmm_234_20": "fmm_423_20", "fmm_432_20": "fmm_423_20",
+             "fmm_442_26": "fmm_424_26", "fmm_244_26": "fmm_424_26",
+             "fmm_232_11": "fmm_223_11", "fmm_322_11": "fmm_223_11",
+             "fmm_252_18": "fmm_225_18", "fmm_522_18": "fmm_225_18"}
+
+
 def get(name) -> Algorithm:
     if name == "strassen_222_7":
         return strassen()
@@ -156,6 +237,13 @@ def get(name) -> Algorithm:
         return classical_222()
     if name == "fmm_333_23":
         return laderman_333()
+    if name == "fmm_223_11":
+        # Strassen on two block columns of B and C, classical on the third
+        return direct_sum_n([strassen(), classical(2, 2, 1)], name)
+    if name == "fmm_225_18":
+        return direct_sum_n([strassen(), strassen(), classical(2, 2, 1)], name)
+    if name in _PERMUTED:
+        return permuted(get(_PERMUTED[name]), _dims(name), name)
     path = os.path.join(_HERE, "tables", name + ".txt")
     if os.path.exists(path):
         return load_table(path, name)
@@ -163,7 +251,8 @@ def get(name) -> Algorithm:
 
 
 def names() -> List[str]:
-    out = ["classical_222_8", "strassen_222_7", "fmm_333_23"]
+    out = ["classical_222_8", "strassen_222_7", "fmm_333_23", "fmm_223_11", "fmm_225_18"]
+    out += sorted(_PERMUTED)
     for fn in sorted(os.listdir(os.path.join(_HERE, "tables"))):
         if fn.endswith(".txt"):
             out.append(fn[:-4])

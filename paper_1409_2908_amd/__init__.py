@@ -343,7 +343,7 @@ def multiply_batched(plans, As, Bs, Cs=None, stream=None):
     return outs
 
 
-def rank_candidates(m, k, n, dtype=F64, alg=None, budget_bytes=0, max_count=64, max_error=0.0):
+def rank_candidates(m, k, n, dtype=F64, alg=None, budget_bytes=0, max_count=4096, max_error=0.0):
     """The cost model's candidates (fmm_rank_candidates), best predicted first;
     max_error 0 applies the dtype's default error budget, < 0 none."""
     out = (_Candidate * max_count)()

@@ -1,7 +1,8 @@
 """Build the HIP library libfmm.so in-tree for gfx950 (MI355X).
 
-Steps: regenerate csrc/fmm_tables.h from the base-case tables, compile every
-source with hipcc in parallel, link one shared library next to this file.
+Steps: regenerate csrc/fmm_tables.h and the per-base-case kernel sources
+(csrc/gen/) from the base-case tables, compile every source with hipcc in
+parallel, link one shared library next to this file.
 """
 import concurrent.futures as cf
 import os
@@ -13,6 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfmm.so")
 SOURCES = ["fmm_api.cpp", "fmm_plan.cpp", "fmm_tune.cpp", "fmm_serve.cpp", "fmm_add.hip", "fmm_gemm.hip", "fmm_gemm_bf16x3.hip"]
+# plus one generated source per base case (csrc/gen/fmm_add_NN.hip), listed by gen_tables.generate()
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -20,7 +22,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 
 
 def _compile(src, verbose):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    obj = os.path.join(BUILD, src.replace("/", "_") + ".o")
     cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -41,10 +43,13 @@ def build(verbose=False):
         "fmm_gen_tables", os.path.join(HERE, "algorithms", "gen_tables.py"))
     gen_tables = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(gen_tables)
-    gen_tables.generate()
+    _, generated = gen_tables.generate()
+    sources = SOURCES + generated
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    # the longest compiles (generated kernels of the widest base cases) first
+    sources.sort(key=lambda s: (not s.startswith("gen/"), s), reverse=False)
+    with cf.ThreadPoolExecutor(max_workers=min(os.cpu_count() or 8, 16)) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), sources))
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -1,561 +1,67 @@
-// Streaming addition kernels: operand formation (S_r from A with U, T_r from B
-// with V) and the W-combination of the leaf products into C.
-//
-// Section 3.2 of the paper compares pairwise, write-once and streaming
-// addition chains.  Here one thread owns one element position (p, q) of the
-// output blocks: it reads the (BR*BC)^lv source elements at that position
-// exactly once, keeps every partial sum in registers, and writes each
-// materialised output exactly once -- the streaming variant's read count with
-// the write-once variant's single output stream per store instruction.  A
-// wavefront covers 64 consecutive q, so every load and store instruction moves
-// 512 contiguous bytes (FP64).  Up to two recursion levels are fused per pass
-// (their Kronecker-product coefficients are applied level by level, top level
-// first, which is the recursion's own order): in registers for narrow base
-// cases (R <= 8), and through LDS for wide ones, where a workgroup stages the
-// (BR*BC)^2 sources (formation) or the R^2 products (combination) of 64
-// positions once and its wavefronts share the level-one sums; the two-level
-// combination always takes the LDS path.  Every variant performs the same
-// roundings in the same order, so fused and one-level passes agree bit for
-// bit.
+// Dispatch of the addition kernels by base case: every base case's
+// launchers are instantiated in a generated source file of their own
+// (csrc/gen/fmm_add_NN.hip, one per table), so they compile in parallel; this
+// file maps the run-time algorithm id to them.
 #include <hip/hip_runtime.h>
 
-#include "fmm_device.h"
+#include <array>
+#include <utility>
+
 #include "fmm_launch.h"
 
 namespace fmm {
 
-constexpr int kAddTX = 64, kAddTY = 4;
-
-__device__ __forceinline__ void store_out(char* ws, int elt, int64_t idx, int64_t plane, double v) {
-  if (elt == ELT_F64) {
-    ((double*)ws)[idx] = v;
-  } else if (elt == ELT_F32) {
-    ((float*)ws)[idx] = (float)v;  // one round-to-nearest-even from the FP64 sum
-  } else {
-    // BF16x3 leaf operand: the FP32 value x of the sum, then its split
-    unsigned short hi, lo;
-    split_bits((float)v, &hi, &lo);
-    ((unsigned short*)ws)[idx] = hi;
-    ((unsigned short*)ws)[idx + plane] = lo;
-  }
-}
-
-// OCT: the output is a split T operand stored in k-octets; each wavefront
-// then covers 8 consecutive rows p of 8 consecutive columns q, so every
-// 2-byte store instruction of the wavefront fills 128 contiguous bytes (8
-// whole octets) instead of scattering over 1 KB.
-template <int ID, int SIDE, int LV, bool OCT>
-__device__ __forceinline__ void form_body(const FormArgs& a, unsigned bx, unsigned by, unsigned bz) {
-  using S = Side<ID, SIDE>;
-  constexpr int NB = S::NB, R = S::R, BR = S::BR, BC = S::BC;
-  constexpr int NIN = LV == 1 ? NB : NB * NB;
-  const int t = threadIdx.y * kAddTX + threadIdx.x;
-  const int64_t q = OCT ? (int64_t)bx * 32 + (t >> 3) : (int64_t)bx * kAddTX + threadIdx.x;
-  const int64_t p = OCT ? (int64_t)by * 8 + (t & 7) : (int64_t)by * kAddTY + threadIdx.y;
-  if (q >= a.w || p >= a.h) return;
-  const int g = (int)bz;
-  const Ref src = a.groups[g];
-  int64_t ld;
-  const char* base = buf_ptr(a.bases, src, &ld);
-  const int64_t h = a.h, w = a.w;
-  double x[NIN];
-  static_for<0, NIN>([&](auto ic) {
-    constexpr int idx = decltype(ic)::value;
-    constexpr int i1 = LV == 1 ? idx : idx / NB;
-    constexpr int i2 = LV == 1 ? 0 : idx % NB;
-    constexpr int a1 = i1 / BC, b1 = i1 % BC, a2 = i2 / BC, b2 = i2 % BC;
-    const int64_t row = src.row + (LV == 1 ? a1 * h : (a1 * BR + a2) * h) + p;
-    const int64_t col = src.col + (LV == 1 ? b1 * w : (b1 * BC + b2) * w) + q;
-    x[idx] = load_elt(base, src.elt, src.off + row * ld + col) * src.alpha;
-  });
-  char* ws = (char*)a.bases.ptr[BUF_WS];
-  const int64_t* outs = a.outs + (int64_t)g * a.nout;
-  // split T operands are stored in k-octets (see Elt): row p, column q
-  const int64_t pos = (SIDE == 1 && a.out_elt == ELT_BF16X2) ? (p >> 3) * a.out_ld + q * 8 + (p & 7)
-                                                            : p * a.out_ld + q;
-  if constexpr (LV == 1) {
-    static_for<0, R>([&](auto rc) {
-      constexpr int r = decltype(rc)::value;
-      const int64_t off = outs[r];
-      if (off >= 0) store_out(ws, a.out_elt, off + pos, a.out_plane, chain_col<S, r, 1, NB>(x));
-    });
-  } else {
-    static_for<0, R>([&](auto r1c) {
-      constexpr int r1 = decltype(r1c)::value;
-      double y[NB];
-      // top level: y[i2] = sum_i1 U[i1][r1] x[i1][i2]
-      static_for<0, NB>([&](auto i2c) {
-        constexpr int i2 = decltype(i2c)::value;
-        y[i2] = chain_col<S, r1, NB, NB>(x + i2);
-      });
-      static_for<0, R>([&](auto r2c) {
-        constexpr int r2 = decltype(r2c)::value;
-        const int64_t off = outs[r1 * R + r2];
-        if (off >= 0) store_out(ws, a.out_elt, off + pos, a.out_plane, chain_col<S, r2, 1, NB>(y));
-      });
-    });
-  }
-}
-
-template <int ID, int SIDE, int LV, bool OCT = false>
-__global__ void __launch_bounds__(kAddTX * kAddTY) form_kernel(FormArgs a) {
-  form_body<ID, SIDE, LV, OCT>(a, blockIdx.x, blockIdx.y, blockIdx.z);
-}
-
-// One level of S and of T in a single launch, for small problems where the
-// idle time between dependent launches is comparable to a pass: blocks
-// [0, xs) of the x dimension form S on an xs x ys x zs grid, the rest form T
-// on its own yt x zt extent; blocks outside a side's grid do nothing.  The
-// body (and so every stored value) is the one form_kernel runs.
 template <int ID>
-__global__ void __launch_bounds__(kAddTX * kAddTY) form_pair_kernel(FormArgs s, FormArgs t, unsigned xs,
-                                                                    unsigned ys, unsigned zs, unsigned yt,
-                                                                    unsigned zt) {
-  if (blockIdx.x < xs) {
-    if (blockIdx.y < ys && blockIdx.z < zs) form_body<ID, 0, 1, false>(s, blockIdx.x, blockIdx.y, blockIdx.z);
-  } else if (blockIdx.y < yt && blockIdx.z < zt) {
-    form_body<ID, 1, 1, false>(t, blockIdx.x - xs, blockIdx.y, blockIdx.z);
-  }
-}
-
-
-// Coefficients of one side as a device table with one row of NB integers per
-// output r, so a wave-uniform r reads its row with scalar loads.
-template <int ID, int SIDE>
-struct ColTable {
-  int c[Side<ID, SIDE>::R][Side<ID, SIDE>::NB];
-};
-
-template <int ID, int SIDE>
-constexpr ColTable<ID, SIDE> make_col_table() {
-  ColTable<ID, SIDE> t{};
-  for (int r = 0; r < Side<ID, SIDE>::R; ++r)
-    for (int i = 0; i < Side<ID, SIDE>::NB; ++i) t.c[r][i] = Side<ID, SIDE>::coef(i, r);
-  return t;
-}
-
-template <int ID, int SIDE>
-__constant__ ColTable<ID, SIDE> kColTable = make_col_table<ID, SIDE>();
-
-// Two levels of operand formation in one pass for wide base cases, staged
-// through LDS.  A workgroup owns 64 consecutive columns q of one row p of
-// the leaf-sized grid: it first loads the NB^2 source elements of those 64
-// positions into LDS (every load instruction of a wavefront reads 512
-// contiguous bytes and a thread has NB^2 / 4 loads in flight), then each
-// wavefront takes every fourth top-level output r1, forms the NB level-two
-// sums y[i2] = sum_i1 U[i1][r1] x[i1][i2] from LDS, and writes
-// S_{r1,r2} = sum_i2 U[i2][r2] y[i2] for every r2.  Sums run in ascending
-// index order from -0.0 with fused multiply-adds: with coefficients +-2^e the
-// first step returns c*x exactly and every later one rounds like the
-// corresponding add or subtract of the chain, so the results equal the
-// register kernel's bit for bit.
-template <int ID, int SIDE>
-__global__ void __launch_bounds__(256) form2_kernel(FormArgs a) {
-  using S = Side<ID, SIDE>;
-  constexpr int NB = S::NB, R = S::R, BR = S::BR, BC = S::BC, NIN = NB * NB;
-  __shared__ double xs[NIN][64];
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
-  const int64_t p = blockIdx.y;
-  const int g = blockIdx.z;
-  const bool valid = q < a.w;
-  const Ref src = a.groups[g];
-  int64_t ld;
-  const char* base = buf_ptr(a.bases, src, &ld);
-  const int64_t h = a.h, w = a.w;
-  // Branch-free loads, all in flight before the first LDS store: lanes past
-  // the last column read column w - 1 and store 0.
-  const int64_t qc = valid ? q : w - 1;
-  constexpr int NJ = (NIN + 3) / 4;
-  double v[NJ];
-  auto load_all = [&](auto tag) {
-    using T = decltype(tag);
-    const T* bp = (const T*)base + src.off;
-#pragma unroll
-    for (int k = 0; k < NJ; ++k) {
-      const int idx = wave + 4 * k < NIN ? wave + 4 * k : NIN - 1;
-      const int i1 = idx / NB, i2 = idx % NB;
-      const int a1 = i1 / BC, b1 = i1 % BC, a2 = i2 / BC, b2 = i2 % BC;
-      const int64_t row = src.row + (a1 * BR + a2) * h + p;
-      const int64_t col = src.col + (b1 * BC + b2) * w + qc;
-      v[k] = (double)bp[row * ld + col];
-    }
-  };
-  if (src.elt == ELT_F64) load_all(double{});
-  else load_all(float{});
-#pragma unroll
-  for (int k = 0; k < NJ; ++k)
-    if (wave + 4 * k < NIN) xs[wave + 4 * k][lane] = valid ? v[k] * src.alpha : 0.0;
-  __syncthreads();
-  if (!valid) return;
-  char* ws = (char*)a.bases.ptr[BUF_WS];
-  const int64_t* outs = a.outs + (int64_t)g * a.nout;
-  const int64_t pos = p * a.out_ld + q;
-  const ColTable<ID, SIDE>& tab = kColTable<ID, SIDE>;
-  for (int r1 = wave; r1 < R; r1 += 4) {
-    double y[NB];
-#pragma unroll
-    for (int i2 = 0; i2 < NB; ++i2) {
-      double acc = -0.0;
-#pragma unroll
-      for (int i1 = 0; i1 < NB; ++i1) {
-        const int c = tab.c[r1][i1];
-        if (c != 0) acc = __fma_rn((double)c, xs[i1 * NB + i2][lane], acc);
-      }
-      y[i2] = acc;
-    }
-    const int64_t* o = outs + r1 * R;
-    static_for<0, R>([&](auto r2c) {
-      constexpr int r2 = decltype(r2c)::value;
-      const int64_t off = o[r2];
-      if (off >= 0) store_out(ws, a.out_elt, off + pos, a.out_plane, chain_col<S, r2, 1, NB>(y));
-    });
-  }
-}
-
-// Split (BF16x3) leaf operands (one level, or two levels of a narrow base
-// case) with two positions per thread, so each store instruction writes two
-// bf16 of a plane (4 bytes per lane) instead of one.  S operands (row-major planes): positions (p, q) and
-// (p, q + 1), a wavefront covering 128 consecutive columns.  T operands
-// (k-octets): positions (p, q) and (p + 1, q) of one octet, a wavefront
-// covering 16 columns of one octet (256 contiguous bytes per plane).  Same
-// chains, in the same order, as form_kernel.
-template <int ID, int SIDE, int LV>
-__global__ void __launch_bounds__(256) form_split2_kernel(FormArgs a) {
-  using S = Side<ID, SIDE>;
-  constexpr int NB = S::NB, R = S::R, BR = S::BR, BC = S::BC;
-  constexpr int NIN = LV == 1 ? NB : NB * NB;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int64_t p, q;
-  constexpr int dp = SIDE == 0 ? 0 : 1, dq = SIDE == 0 ? 1 : 0;
-  if constexpr (SIDE == 0) {
-    q = ((int64_t)blockIdx.x * 64 + lane) * 2;
-    p = (int64_t)blockIdx.y * 4 + wave;
-  } else {
-    q = (int64_t)blockIdx.x * 64 + wave * 16 + (lane >> 2);
-    p = (int64_t)blockIdx.y * 8 + 2 * (lane & 3);
-  }
-  if (q >= a.w || p >= a.h) return;
-  const bool two = q + dq < a.w && p + dp < a.h;
-  const int g = blockIdx.z;
-  const Ref src = a.groups[g];
-  int64_t ld;
-  const char* base = buf_ptr(a.bases, src, &ld);
-  const int64_t h = a.h, w = a.w;
-  double x0[NIN], x1[NIN];
-  static_for<0, NIN>([&](auto ic) {
-    constexpr int idx = decltype(ic)::value;
-    constexpr int i1 = LV == 1 ? idx : idx / NB;
-    constexpr int i2 = LV == 1 ? 0 : idx % NB;
-    constexpr int a1 = i1 / BC, b1 = i1 % BC, a2 = i2 / BC, b2 = i2 % BC;
-    const int64_t row = src.row + (LV == 1 ? a1 * h : (a1 * BR + a2) * h) + p;
-    const int64_t col = src.col + (LV == 1 ? b1 * w : (b1 * BC + b2) * w) + q;
-    const int64_t e = src.off + row * ld + col;
-    x0[idx] = load_elt(base, src.elt, e) * src.alpha;
-    x1[idx] = load_elt(base, src.elt, two ? e + dp * ld + dq : e) * src.alpha;
-  });
-  unsigned short* ws = (unsigned short*)a.bases.ptr[BUF_WS];
-  const int64_t* outs = a.outs + (int64_t)g * a.nout;
-  const int64_t pos = SIDE == 0 ? p * a.out_ld + q : (p >> 3) * a.out_ld + q * 8 + (p & 7);
-  auto put = [&](int64_t off, double v0, double v1) {
-    unsigned short h0, l0, h1, l1;
-    split_bits((float)v0, &h0, &l0);
-    split_bits((float)v1, &h1, &l1);
-    const int64_t i = off + pos;  // even: planes, rows and octets have even lengths
-    if (two) {
-      *(unsigned*)(ws + i) = (unsigned)h0 | ((unsigned)h1 << 16);
-      *(unsigned*)(ws + i + a.out_plane) = (unsigned)l0 | ((unsigned)l1 << 16);
-    } else {
-      ws[i] = h0;
-      ws[i + a.out_plane] = l0;
-    }
-  };
-  if constexpr (LV == 1) {
-    static_for<0, R>([&](auto rc) {
-      constexpr int r = decltype(rc)::value;
-      const int64_t off = outs[r];
-      if (off >= 0) put(off, chain_col<S, r, 1, NB>(x0), chain_col<S, r, 1, NB>(x1));
-    });
-  } else {
-    static_for<0, R>([&](auto r1c) {
-      constexpr int r1 = decltype(r1c)::value;
-      double y0[NB], y1[NB];
-      static_for<0, NB>([&](auto i2c) {
-        constexpr int i2 = decltype(i2c)::value;
-        y0[i2] = chain_col<S, r1, NB, NB>(x0 + i2);
-        y1[i2] = chain_col<S, r1, NB, NB>(x1 + i2);
-      });
-      static_for<0, R>([&](auto r2c) {
-        constexpr int r2 = decltype(r2c)::value;
-        const int64_t off = outs[r1 * R + r2];
-        if (off >= 0) put(off, chain_col<S, r2, 1, NB>(y0), chain_col<S, r2, 1, NB>(y1));
-      });
-    });
-  }
-}
-
-// W-combination, one level: C_k = sum_r W[k][r] M_r at each position.
+hipError_t launch_form_id(const FormArgs& a, int side, int lv, int ngroups, hipStream_t s);
 template <int ID>
-__global__ void __launch_bounds__(kAddTX * kAddTY) combine1_kernel(CombineArgs a) {
-  using CB = Comb<ID>;
-  constexpr int R = CB::R, MN = CB::MN, N = Alg<ID>::N;
-  const int64_t q = (int64_t)blockIdx.x * kAddTX + threadIdx.x;
-  const int64_t p = (int64_t)blockIdx.y * kAddTY + threadIdx.y;
-  if (q >= a.w || p >= a.h) return;
-  const int g = blockIdx.z;
-  const char* ws = (const char*)a.bases.ptr[BUF_WS];
-  const int64_t in0 = a.in_off[g] + p * a.in_ld + q;
-  double mv[R];
-  static_for<0, R>([&](auto rc) {
-    constexpr int r = decltype(rc)::value;
-    mv[r] = load_elt(ws, a.in_elt, in0 + r * a.in_stride);
-  });
-  const Ref out = a.out[g];
-  int64_t ld;
-  char* ob = buf_ptr(a.bases, out, &ld);
-  int64_t pld = 0;
-  const char* pb = a.has_p ? buf_ptr(a.bases, a.p, &pld) : nullptr;
-  static_for<0, MN>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    constexpr int ba = k / N, bc = k % N;
-    double v = chain_row<ID, k>(mv);
-    const int64_t row = ba * a.h + p, col = bc * a.w + q;
-    if (a.has_p) v = __dadd_rn(v, load_elt(pb, a.p.elt, a.p.off + row * pld + col));
-    const int64_t idx = out.off + (out.row + row) * ld + out.col + col;
-    if (out.elt == ELT_F64) ((double*)ob)[idx] = v;
-    else ((float*)ob)[idx] = (float)v;
-  });
+hipError_t launch_form_pair_id(const FormArgs& sa, int ngs, const FormArgs& ta, int ngt, hipStream_t st);
+template <int ID>
+hipError_t launch_combine_id(const CombineArgs& a, int lv, int ngroups, hipStream_t s);
+
+namespace {
+
+using FormFn = hipError_t (*)(const FormArgs&, int, int, int, hipStream_t);
+using PairFn = hipError_t (*)(const FormArgs&, int, const FormArgs&, int, hipStream_t);
+using CombFn = hipError_t (*)(const CombineArgs&, int, int, hipStream_t);
+
+template <int... I>
+constexpr auto form_table(std::integer_sequence<int, I...>) {
+  return std::array<FormFn, sizeof...(I)>{&launch_form_id<I>...};
+}
+template <int... I>
+constexpr auto pair_table(std::integer_sequence<int, I...>) {
+  return std::array<PairFn, sizeof...(I)>{&launch_form_pair_id<I>...};
+}
+template <int... I>
+constexpr auto comb_table(std::integer_sequence<int, I...>) {
+  return std::array<CombFn, sizeof...(I)>{&launch_combine_id<I>...};
 }
 
-template <int ID>
-struct WTable {
-  int c[Comb<ID>::MN][Comb<ID>::R];
-};
+const auto kFormFns = form_table(std::make_integer_sequence<int, kNumAlgorithms>{});
+const auto kPairFns = pair_table(std::make_integer_sequence<int, kNumAlgorithms>{});
+const auto kCombFns = comb_table(std::make_integer_sequence<int, kNumAlgorithms>{});
 
-template <int ID>
-constexpr WTable<ID> make_w_table() {
-  WTable<ID> t{};
-  for (int k = 0; k < Comb<ID>::MN; ++k)
-    for (int r = 0; r < Comb<ID>::R; ++r) t.c[k][r] = Comb<ID>::coef(k, r);
-  return t;
-}
-
-template <int ID>
-__constant__ WTable<ID> kWTable = make_w_table<ID>();
-
-// W-combination, two levels fused, for wide base cases.  A workgroup of four
-// wavefronts owns 64 consecutive positions of one row; wavefront w owns the
-// top-level output blocks c1 = w, w+4, ... and accumulates C_{c1,c2} for
-// every deeper block c2 in registers.  The products are staged through LDS
-// RC top-level indices r1 at a time (R*RC*64 elements, every element read
-// from HBM once, RC*R/4 loads in flight per thread); from LDS each wavefront
-// forms Y_{r1,c2} = sum_r2 W[c2][r2] M_{r1,r2} for all c2 (compile-time
-// chains) and adds W[c1][r1] Y_{r1,c2}.  Same summation order as the
-// one-level passes, so the results are bitwise theirs.
-template <int ID>
-__global__ void __launch_bounds__(256) combine2_kernel(CombineArgs a) {
-  using CB = Comb<ID>;
-  constexpr int R = CB::R, MN = CB::MN, N = Alg<ID>::N, M = Alg<ID>::M;
-  constexpr int RC = 4, CPW = (MN + 3) / 4;
-  constexpr int NLD = RC * R * 64 / 256;  // loads per thread and stage
-  __shared__ double sm[RC * R][64];
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
-  const int64_t p = blockIdx.y;
-  const int g = blockIdx.z;
-  const char* ws = (const char*)a.bases.ptr[BUF_WS];
-  const int64_t gbase = a.in_off[g] + p * a.in_ld;
-  const WTable<ID>& tab = kWTable<ID>;
-  double acc[CPW][MN];
-#pragma unroll
-  for (int cc = 0; cc < CPW; ++cc)
-#pragma unroll
-    for (int c2 = 0; c2 < MN; ++c2) acc[cc][c2] = -0.0;
-  for (int r0 = 0; r0 < R; r0 += RC) {
-    double v[NLD];
-#pragma unroll
-    for (int j = 0; j < NLD; ++j) {
-      const int e = (int)threadIdx.x + 256 * j;
-      const int rr = e >> 6, l = e & 63;
-      const int64_t qq = (int64_t)blockIdx.x * 64 + l;
-      v[j] = (r0 * R + rr < R * R && qq < a.w)
-                 ? load_elt(ws, a.in_elt, gbase + (int64_t)(r0 * R + rr) * a.in_stride + qq)
-                 : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < NLD; ++j) {
-      const int e = (int)threadIdx.x + 256 * j;
-      sm[e >> 6][e & 63] = v[j];
-    }
-    __syncthreads();
-    for (int j = 0; j < RC && r0 + j < R; ++j) {
-      const int r1 = r0 + j;
-      double y[MN];
-      static_for<0, MN>([&](auto c2c) {
-        constexpr int c2 = decltype(c2c)::value;
-        double t = -0.0;
-        static_for<0, R>([&](auto r2c) {
-          constexpr int r2 = decltype(r2c)::value;
-          constexpr int c = CB::coef(c2, r2);
-          if constexpr (c != 0) t = __fma_rn((double)c, sm[j * R + r2][lane], t);
-        });
-        y[c2] = t;
-      });
-#pragma unroll
-      for (int cc = 0; cc < CPW; ++cc) {
-        const int c1 = wave + 4 * cc;
-        if (c1 < MN) {
-          const int c = tab.c[c1][r1];
-          if (c != 0) {
-#pragma unroll
-            for (int c2 = 0; c2 < MN; ++c2) acc[cc][c2] = __fma_rn((double)c, y[c2], acc[cc][c2]);
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if (q >= a.w) return;
-  const Ref out = a.out[g];
-  int64_t ld;
-  char* ob = buf_ptr(a.bases, out, &ld);
-  int64_t pld = 0;
-  const char* pb = a.has_p ? buf_ptr(a.bases, a.p, &pld) : nullptr;
-#pragma unroll
-  for (int cc = 0; cc < CPW; ++cc) {
-    const int c1 = wave + 4 * cc;
-    if (c1 >= MN) continue;
-    const int a1 = c1 / N, cc1 = c1 % N;
-#pragma unroll
-    for (int c2 = 0; c2 < MN; ++c2) {
-      const int a2 = c2 / N, cc2 = c2 % N;
-      const int64_t row = (int64_t)(a1 * M + a2) * a.h + p;
-      const int64_t col = (int64_t)(cc1 * N + cc2) * a.w + q;
-      double v = acc[cc][c2];
-      if (a.has_p) v = __dadd_rn(v, load_elt(pb, a.p.elt, a.p.off + row * pld + col));
-      const int64_t idx = out.off + (out.row + row) * ld + out.col + col;
-      if (out.elt == ELT_F64) ((double*)ob)[idx] = v;
-      else ((float*)ob)[idx] = (float)v;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// host launchers
-
-template <int ID>
-static hipError_t launch_form_id(const FormArgs& a, int side, int lv, int ngroups, hipStream_t s) {
-  dim3 block(kAddTX, kAddTY);
-  if (a.out_elt == ELT_BF16X2 && (lv == 1 || (lv == 2 && Alg<ID>::R <= 8))) {
-    const dim3 g2 = side == 0 ? dim3((unsigned)((a.w + 127) / 128), (unsigned)((a.h + 3) / 4), (unsigned)ngroups)
-                              : dim3((unsigned)((a.w + 63) / 64), (unsigned)((a.h + 7) / 8), (unsigned)ngroups);
-    if (side == 0 && lv == 1) hipLaunchKernelGGL((form_split2_kernel<ID, 0, 1>), g2, dim3(256), 0, s, a);
-    else if (side == 1 && lv == 1) hipLaunchKernelGGL((form_split2_kernel<ID, 1, 1>), g2, dim3(256), 0, s, a);
-    else if constexpr (Alg<ID>::R <= 8) {
-      if (side == 0) hipLaunchKernelGGL((form_split2_kernel<ID, 0, 2>), g2, dim3(256), 0, s, a);
-      else hipLaunchKernelGGL((form_split2_kernel<ID, 1, 2>), g2, dim3(256), 0, s, a);
-    }
-    return hipGetLastError();
-  }
-  if constexpr (Alg<ID>::R > 8) {
-    // split T operands of two fused levels of a wide base case: the register
-    // kernel with the 8 x 8 wavefront mapping of the k-octet layout
-    if (side == 1 && a.out_elt == ELT_BF16X2 && lv == 2) {
-      dim3 grid((unsigned)((a.w + 31) / 32), (unsigned)((a.h + 7) / 8), (unsigned)ngroups);
-      hipLaunchKernelGGL((form_kernel<ID, 1, 2, true>), grid, block, 0, s, a);
-      return hipGetLastError();
-    }
-  }
-  // Two fused levels of a wide base case go through LDS, except split T
-  // operands (k-octet layout), which keep the register kernel's 8 x 8 mapping.
-  if (lv == 2 && Alg<ID>::R > 8 && !(side == 1 && a.out_elt == ELT_BF16X2)) {
-    dim3 g2((unsigned)((a.w + 63) / 64), (unsigned)a.h, (unsigned)ngroups);
-    if (side == 0) hipLaunchKernelGGL((form2_kernel<ID, 0>), g2, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((form2_kernel<ID, 1>), g2, dim3(256), 0, s, a);
-    return hipGetLastError();
-  }
-  dim3 grid((unsigned)((a.w + kAddTX - 1) / kAddTX), (unsigned)((a.h + kAddTY - 1) / kAddTY),
-            (unsigned)ngroups);
-  if (side == 0 && lv == 1) hipLaunchKernelGGL((form_kernel<ID, 0, 1>), grid, block, 0, s, a);
-  else if (side == 1 && lv == 1) hipLaunchKernelGGL((form_kernel<ID, 1, 1>), grid, block, 0, s, a);
-  else if constexpr (Alg<ID>::R <= 8) {
-    if (side == 0 && lv == 2) hipLaunchKernelGGL((form_kernel<ID, 0, 2>), grid, block, 0, s, a);
-    else if (side == 1 && lv == 2) hipLaunchKernelGGL((form_kernel<ID, 1, 2>), grid, block, 0, s, a);
-    else return hipErrorInvalidValue;
-  } else {
-    return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template <int ID>
-static hipError_t launch_form_pair_id(const FormArgs& sa, int ngs, const FormArgs& ta, int ngt, hipStream_t st) {
-  const unsigned xs = (unsigned)((sa.w + kAddTX - 1) / kAddTX), ys = (unsigned)((sa.h + kAddTY - 1) / kAddTY);
-  const unsigned xt = (unsigned)((ta.w + kAddTX - 1) / kAddTX), yt = (unsigned)((ta.h + kAddTY - 1) / kAddTY);
-  const dim3 grid(xs + xt, ys > yt ? ys : yt, (unsigned)(ngs > ngt ? ngs : ngt));
-  hipLaunchKernelGGL((form_pair_kernel<ID>), grid, dim3(kAddTX, kAddTY), 0, st, sa, ta, xs, ys, (unsigned)ngs, yt,
-                     (unsigned)ngt);
-  return hipGetLastError();
-}
+}  // namespace
 
 hipError_t launch_form_pair(int alg, const FormArgs& sa, int ngs, const FormArgs& ta, int ngt, hipStream_t st) {
   // one-level passes with unsplit outputs and non-empty grids on both sides
   if (sa.out_elt == ELT_BF16X2 || ta.out_elt == ELT_BF16X2 || sa.h <= 0 || sa.w <= 0 || ta.h <= 0 || ta.w <= 0 ||
       ngs <= 0 || ngt <= 0)
     return hipErrorInvalidValue;
-  switch (alg) {
-    case 0: return launch_form_pair_id<0>(sa, ngs, ta, ngt, st);
-    case 1: return launch_form_pair_id<1>(sa, ngs, ta, ngt, st);
-    case 2: return launch_form_pair_id<2>(sa, ngs, ta, ngt, st);
-    case 3: return launch_form_pair_id<3>(sa, ngs, ta, ngt, st);
-    case 4: return launch_form_pair_id<4>(sa, ngs, ta, ngt, st);
-    case 5: return launch_form_pair_id<5>(sa, ngs, ta, ngt, st);
-  }
-  return hipErrorInvalidValue;
+  if (alg < 0 || alg >= kNumAlgorithms) return hipErrorInvalidValue;
+  return kPairFns[alg](sa, ngs, ta, ngt, st);
 }
 
 hipError_t launch_form(int alg, const FormArgs& a, int side, int lv, int ngroups, hipStream_t s) {
   if (a.h == 0 || a.w == 0 || ngroups == 0) return hipSuccess;
-  switch (alg) {
-    case 0: return launch_form_id<0>(a, side, lv, ngroups, s);
-    case 1: return launch_form_id<1>(a, side, lv, ngroups, s);
-    case 2: return launch_form_id<2>(a, side, lv, ngroups, s);
-    case 3: return launch_form_id<3>(a, side, lv, ngroups, s);
-    case 4: return launch_form_id<4>(a, side, lv, ngroups, s);
-    case 5: return launch_form_id<5>(a, side, lv, ngroups, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <int ID>
-static hipError_t launch_combine_id(const CombineArgs& a, int lv, int ngroups, hipStream_t s) {
-  if (lv == 1) {
-    dim3 block(kAddTX, kAddTY);
-    dim3 grid((unsigned)((a.w + kAddTX - 1) / kAddTX), (unsigned)((a.h + kAddTY - 1) / kAddTY),
-              (unsigned)ngroups);
-    hipLaunchKernelGGL((combine1_kernel<ID>), grid, block, 0, s, a);
-  } else if (lv == 2) {
-    dim3 grid((unsigned)((a.w + 63) / 64), (unsigned)a.h, (unsigned)ngroups);
-    hipLaunchKernelGGL((combine2_kernel<ID>), grid, dim3(256), 0, s, a);
-  } else {
-    return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  if (alg < 0 || alg >= kNumAlgorithms) return hipErrorInvalidValue;
+  return kFormFns[alg](a, side, lv, ngroups, s);
 }
 
 hipError_t launch_combine(int alg, const CombineArgs& a, int lv, int ngroups, hipStream_t s) {
   if (a.h == 0 || a.w == 0 || ngroups == 0) return hipSuccess;
-  switch (alg) {
-    case 0: return launch_combine_id<0>(a, lv, ngroups, s);
-    case 1: return launch_combine_id<1>(a, lv, ngroups, s);
-    case 2: return launch_combine_id<2>(a, lv, ngroups, s);
-    case 3: return launch_combine_id<3>(a, lv, ngroups, s);
-    case 4: return launch_combine_id<4>(a, lv, ngroups, s);
-    case 5: return launch_combine_id<5>(a, lv, ngroups, s);
-  }
-  return hipErrorInvalidValue;
+  if (alg < 0 || alg >= kNumAlgorithms) return hipErrorInvalidValue;
+  return kCombFns[alg](a, lv, ngroups, s);
 }
 
 }  // namespace fmm

@@ -197,9 +197,6 @@ hipError_t run_combine(const fmm::Plan& P, const fmm::Bases& b, hipStream_t s) {
     a.in_elt = cp.in_elt;
     a.has_p = cp.has_p ? 1 : 0;
     a.p = cp.p;
-    const fmm::AlgInfo& A = fmm::alg_info(cp.alg);
-    for (int k = 0; k < A.M * A.N; ++k)
-      for (int r = 0; r < A.R; ++r) a.wc[k][r] = A.W[k * A.R + r];
     hipError_t e = fmm::launch_combine(cp.alg, a, cp.lv, cp.ngroups, s);
     if (e != hipSuccess) return e;
   }

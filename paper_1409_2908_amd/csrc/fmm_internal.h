@@ -128,8 +128,6 @@ struct FormArgs {
   int64_t out_plane;
 };
 
-constexpr int kMaxMN = 16, kMaxR = 32;
-
 struct CombineArgs {
   Bases bases;
   const int64_t* in_off;
@@ -138,7 +136,6 @@ struct CombineArgs {
   int in_elt;
   int has_p;
   Ref p;
-  signed char wc[kMaxMN][kMaxR];  // W[k][r] for kernels that index it at run time
 };
 
 // --- plan -----------------------------------------------------------------

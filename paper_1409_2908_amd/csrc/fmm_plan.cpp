@@ -52,9 +52,20 @@ int col_nnz(const signed char* X, int rows, int R, int r, int* where, int* coef)
 // plans of wide base cases (R > 8), whose split T operands in k-octets are
 // formed by the register kernel, which measured slower fused than unfused.
 // Plans whose levels use different base cases always run one level per pass.
+// Whether base case `id` can fuse two levels per addition pass: narrow ones
+// (R <= 8) in registers, wide ones through LDS, which holds the (BR*BC)^2
+// sources of 64 positions (at most 11 blocks per side) and the products of 4
+// top-level indices (R <= 32).  The kernels compile the two-level variants
+// only for these (kFuse2 in fmm_add_kernels.h states the same rule).
+bool fuse2_ok(int id) {
+  const AlgInfo& a = alg_info(id);
+  return a.R <= 8 || (a.M * a.K <= 11 && a.K * a.N <= 11 && a.R <= 32);
+}
+
 int resolve_fuse(int requested, int R, int dtype, const std::vector<int>& ids) {
   for (int id : ids)
     if (id != ids[0]) return 1;  // levels of different base cases: one level per pass
+  if (!ids.empty() && !fuse2_ok(ids[0])) return 1;  // too wide for the two-level kernels
   if (requested == 1 || requested == 2) return requested;
   const char* e = std::getenv("FMM_FUSE");
   if (e && (e[0] == '1' || e[0] == '2') && e[1] == 0) return e[0] - '0';

@@ -14,7 +14,7 @@ import paper_1409_2908_amd as F
 from oracle import algorithms, tensor
 from conftest import ROOT
 
-ALGS = ["strassen_222_7", "fmm_333_23", "fmm_323_15", "fmm_423_20", "fmm_424_26", "classical_222_8"]
+ALGS = algorithms.names()
 
 
 def test_library_exports_every_declared_symbol():
@@ -36,6 +36,20 @@ def test_compiled_tables_pass_brent_and_match_oracle_copy(name):
     assert U.tolist() == [list(r) for r in a.U]
     assert V.tolist() == [list(r) for r in a.V]
     assert W.tolist() == [list(r) for r in a.W]
+
+
+def test_library_and_oracle_list_the_same_tables():
+    assert sorted(F.algorithm_names()) == sorted(algorithms.names())
+
+
+def test_two_level_fusion_rule():
+    """Two levels per addition pass for narrow base cases (R <= 8) and for
+    wide ones with at most 11 blocks per side and R <= 32; one otherwise."""
+    for name in algorithms.names():
+        a = algorithms.get(name)
+        ok = a.R <= 8 or (a.M * a.K <= 11 and a.K * a.N <= 11 and a.R <= 32)
+        p = F.Plan(name, a.M ** 2 * 3, a.K ** 2 * 3, a.N ** 2 * 3, 2, host_only=True, fuse_levels=2)
+        assert p.info["fuse_levels"] == (2 if ok else 1), name
 
 
 def test_library_brent_self_check():

@@ -15,6 +15,9 @@ from conftest import load_golden_matrices
 from oracle import algorithms, classical, recursive, tensor
 
 ALGS = ["strassen_222_7", "fmm_333_23", "fmm_323_15", "fmm_423_20", "fmm_424_26"]
+# every fast table: the above, their permutations by Propositions 2.1 / 2.2 and
+# the direct sums <2,2,3;11>, <2,2,5;18> with theirs
+ALL = [n for n in algorithms.names() if n != "classical_222_8"]
 
 
 # --- the matrix-multiplication tensor (Section 2.2) ------------------------
@@ -77,13 +80,13 @@ def _table2():
     return {(r[0], r[1], r[2]): r for r in rows}
 
 
-@pytest.mark.parametrize("name", ALGS + ["classical_222_8"])
+@pytest.mark.parametrize("name", ALL + ["classical_222_8"])
 def test_tables_pass_brent(name):
     a = algorithms.get(name)
     assert tensor.brent_residual(a.U, a.V, a.W, a.M, a.K, a.N) == []
 
 
-@pytest.mark.parametrize("name", ALGS)
+@pytest.mark.parametrize("name", ALL)
 def test_rank_matches_table2(name):
     """The rank R equals Table 2's entry for the base case or one of its
     permutations (<3,2,3> and <4,2,x> are permutations of the printed
@@ -126,7 +129,7 @@ def test_propositions_21_22_give_algorithms(name):
     assert len(seen) == len(set(__import__("itertools").permutations(a.dims)))
 
 
-@pytest.mark.parametrize("name", ALGS)
+@pytest.mark.parametrize("name", ALL)
 def test_brent_catches_planted_mistakes(name):
     """A wrong sign, a dropped term or a moved index in any factor matrix
     must fail the Brent check."""
@@ -489,3 +492,30 @@ def test_bf16x3_gate_catches_a_dropped_cross_term(name, monkeypatch):
     ref = classical.gemm(A, B)
     err = np.linalg.norm(bf16x3.fmm(a, 1, A, B) - ref) / np.linalg.norm(ref)
     assert err > 4 * bf16x3.gate(a, 1, k), (err, bf16x3.gate(a, 1, k))
+
+
+def test_every_shape_of_table2_ranks_up_to_4_has_a_table():
+    """Every permutation of Table 2's exact base cases with all dimensions at
+    most 5 and rank from the tables here is present: <2,2,3;11>, <2,2,5;18>,
+    <2,3,3;15>, <2,3,4;20>, <2,4,4;26> in all their orders, plus <3,3,3;23>."""
+    import itertools
+    have = {algorithms.get(n).dims: algorithms.get(n).R for n in ALL}
+    for base, rank in (((2, 2, 3), 11), ((2, 2, 5), 18), ((2, 3, 3), 15), ((2, 3, 4), 20), ((2, 4, 4), 26),
+                       ((3, 3, 3), 23)):
+        assert _table2()[base][3] == rank
+        for d in set(itertools.permutations(base)):
+            assert have.get(d) == rank, (d, have.get(d))
+
+
+@pytest.mark.parametrize("name", ["fmm_223_11", "fmm_225_18"])
+def test_direct_sums_equal_their_parts(name):
+    """The direct sum along N computes, on each column block of B and C, its
+    part's product: the product with B's other column blocks zeroed equals
+    the part alone (exact on integers)."""
+    a = algorithms.get(name)
+    rng = np.random.default_rng(3)
+    L = 1
+    A = rng.integers(-5, 6, size=(a.M * 3, a.K * 2)).astype(np.float64)
+    B = rng.integers(-5, 6, size=(a.K * 2, a.N * 4)).astype(np.float64)
+    C = recursive.fmm(a, L, A, B)
+    assert np.array_equal(C, A @ B)
