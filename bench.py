@@ -75,7 +75,11 @@ def main():
                          "stream; sweep: timing tables of the square, rectangular and BF16x3 shapes")
     ap.add_argument("--requests", type=int, default=10000, help="serving: stream length")
     ap.add_argument("--load", type=float, default=0.8, help="serving: offered load / measured capacity")
-    ap.add_argument("--arena-gb", type=float, default=96.0, help="serving: workspace arena (GB)")
+    ap.add_argument("--arena-gb", type=float, default=0.0,
+                    help="serving: workspace arena (GB; 0 = the device's free memory less a reserve)")
+    ap.add_argument("--streams", type=int, default=3, help="serving: server streams (1-4)")
+    ap.add_argument("--large-gflop", type=float, default=0.0,
+                    help="serving: 2mkn (GFLOP) from which a request is large (0: the library default)")
     ap.add_argument("--max-batch", type=int, default=8)
     ap.add_argument("--max-inflight", type=int, default=2)
     ap.add_argument("--sweep", default="square", choices=["square", "rect", "bf16x3", "latency"])
@@ -315,7 +319,8 @@ def run_serving(args):
     pools = serving.Pools(8192 + 4096, seed=3)
     arena = int(args.arena_gb * 1e9)
     zeros = np.zeros(len(reqs))
-    common = dict(arena_bytes=arena, max_batch=args.max_batch, max_inflight=args.max_inflight)
+    common = dict(arena_bytes=arena, max_batch=args.max_batch, max_inflight=args.max_inflight,
+                  num_streams=args.streams, large_flops=args.large_gflop * 1e9)
     cap_fast, _ = serving.run_stream(reqs, zeros, pools, **common)
     log(f"[serving] capacity, fast path: {cap_fast}")
     cap_cl, _ = serving.run_stream(reqs, zeros, pools, arena_bytes=arena, max_batch=1, max_inflight=1,
@@ -326,6 +331,9 @@ def run_serving(args):
     keep = set(int(x) for x in np.random.default_rng(13).choice(len(reqs), min(200, len(reqs)), replace=False))
     fast, kept = serving.run_stream(reqs, arr, pools, keep=keep, **common)
     log(f"[serving] Poisson at {rate:.1f} req/s, fast path: {fast}")
+    one = dict(common, num_streams=1)
+    fast1, _ = serving.run_stream(reqs, arr, pools, **one)
+    log(f"[serving] Poisson at {rate:.1f} req/s, fast path on one stream: {fast1}")
     cl, _ = serving.run_stream(reqs, arr, pools, arena_bytes=arena, max_batch=1, max_inflight=1,
                                alg="classical", levels=0)
     log(f"[serving] Poisson at {rate:.1f} req/s, one-at-a-time classical: {cl}")
@@ -344,10 +352,10 @@ def run_serving(args):
         "value": round(fast["req_per_s"], 3), "unit": "requests/s", "n_gpus": 1,
         "higher_is_better": True, "data": "synthetic", "dtype": "f64+f32(bf16x3)",
         "config": {"workload": f"{len(reqs)} requests, m,k,n log-uniform [256,8192], FP64/FP32 1:1, "
-                               f"Poisson at {args.load} x capacity", "arena_gb": args.arena_gb,
-                   "max_batch": args.max_batch, "max_inflight": args.max_inflight},
+                               f"Poisson at {args.load} x capacity", "arena_gb": fast["arena_gb"],
+                   "streams": args.streams, "max_batch": args.max_batch, "max_inflight": args.max_inflight},
         "offered_req_per_s": round(rate, 3),
-        "fast": fast, "classical_one_at_a_time": cl,
+        "fast": fast, "fast_one_stream": fast1, "classical_one_at_a_time": cl,
         "capacity_fast": cap_fast, "capacity_classical": cap_cl,
         "fast_graph": fast_graph, "capacity_fast_graph": cap_graph,
         "alone_vs_mix_checked": checked, "alone_vs_mix_checked_graph": checked_g,
@@ -438,11 +446,12 @@ def run_sweep(args):
             return {"p50_ms": ts[len(ts) // 2], "p99_ms": ts[int(len(ts) * 0.99)], "min_ms": ts[0]}
 
         emit({"shape": [n, n, n], "alg": "classical", "levels": 0, **lat(lambda: F.gemm(A, B, C))})
-        for graph in (False, True):
-            p = F.Plan("strassen_222_7", n, n, n, 1, F.F64, use_graph=graph)
-            emit({"shape": [n, n, n], "alg": "strassen_222_7", "levels": 1, "graph": graph,
-                  **lat(lambda: p.multiply(A, B, C))})
-            p.close()
+        for leaf_form in (1, 2):  # formation passes, or inside the leaf GEMM (the default here)
+            for graph in (False, True):
+                p = F.Plan("strassen_222_7", n, n, n, 1, F.F64, use_graph=graph, leaf_form=leaf_form)
+                emit({"shape": [n, n, n], "alg": "strassen_222_7", "levels": 1, "graph": graph,
+                      "leaf_form": p.info["leaf_form"], **lat(lambda: p.multiply(A, B, C))})
+                p.close()
     else:
         for n in (8192, 16384):
             A, B, C = operands(n, n, n, torch.float32)

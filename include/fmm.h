@@ -100,6 +100,12 @@ typedef struct {
                                     g = sqrt(sum_r |u_r|^2 |v_r|^2 |w_r|^2 / (M K N)) over the
                                     columns of U, V, W (the root-mean-square error growth of one
                                     step for i.i.d. zero-mean operands: 1 classical, 2 Strassen) */
+    int leaf_form;               /* non-zero: the leaf GEMM forms S and T while it stages them
+                                    (this many term slots per operand: 2), and
+                                    fmm_multiply, fmm_multiply_noalloc and fmm_multiply_batched
+                                    enqueue no formation stage; fmm_run_stage still runs
+                                    FMM_STAGE_FORM_S / FORM_T (they write S and T to the
+                                    workspace, where the leaf stage does not read them) */
 } fmm_plan_info_t;
 
 /* Options of fmm_plan_ex.  Zero-initialise, then set what you need. */
@@ -125,6 +131,17 @@ typedef struct {
                           error_bound (fmm_plan_info_t) a chosen plan may have; 0: the dtype's
                           default (1e-12 FP64, 1e-4 FP32, 5e-4 BF16x3); < 0: no limit.
                           Plans named explicitly are not limited. */
+    int leaf_form;     /* where the leaf operands S and T are formed (Section 3.2's
+                          additions): 1 by the formation passes; 2 inside the leaf GEMM,
+                          which loads the A (B) blocks of each S (T) column and sums them
+                          while it stages the tile, in the passes' order and precision, so
+                          the product is bit for bit the same (one-level FP64 / FP32 plans
+                          whose U and V columns have at most 2 non-zeros, all +-1: Strassen
+                          and its direct sums; else FMM_EINVAL); such launches run 64 x 64
+                          tiles whatever leaf_tile asks; 0 (default): 2 when allowed and the
+                          leaf launch has at most 256 tiles of 128 x 128 (it cannot fill the
+                          device, and the formation launch and its idle gap cost more than
+                          the leaves' extra loads), else 1 */
 } fmm_plan_options_t;
 
 /* Plan C = A*B for an m x k by k x n product with `levels` recursive steps of
@@ -320,21 +337,38 @@ fmm_status fmm_tune_clear(void);
 
 /* ---- Serving runtime: continuous batching ---------------------------------
  * A request queue in front of fmm_multiply_batched.  Requests are admitted in
- * arrival order while the device arena (workspaces and descriptor tables)
- * has room and fewer than max_inflight batches are pending; each admitted
- * batch of up to max_batch requests is enqueued as one fmm_multiply_batched
- * (or, with use_graph, as one HIP graph recorded from it) on the server's
- * stream and followed by one completion event.  Planning of
- * the next batch on the host overlaps the running batch on the device.  The
- * caller owns A, B and C of every request and keeps them alive until the
+ * arrival order (within their class, below) while the device arena
+ * (workspaces and descriptor tables) has room and a stream of their class
+ * has fewer than max_inflight batches pending; each admitted batch is
+ * enqueued as one fmm_multiply_batched (or, with use_graph, as one HIP graph
+ * recorded from it) on one of the server's streams and followed by one
+ * completion event there.  With num_streams = 1 every request shares one
+ * stream and batches hold up to max_batch requests.  With 2-4 streams
+ * (each of the default priority), stream 0 runs the large requests
+ * (2mkn >= large_flops) one per batch, shortest first (fewest flops; a
+ * request waiting over 100 ms goes first, oldest first), and the others run
+ * the remaining requests in arrival order, in batches of up to max_batch,
+ * each batch on the one with the fewest pending batches: a small request
+ * never waits behind a large product, and the device interleaves the
+ * streams' workgroups as those of running kernels retire.  Planning
+ * of the next batches on the host overlaps the running ones on the device.
+ * The caller owns A, B and C of every request and keeps them alive until the
  * request completes.  Single-threaded: call every fmm_server_* function of
  * one server from one thread. */
 typedef struct fmm_server_s *fmm_server_t;
 
+/* Default large-request threshold (2mkn, flops) with several streams: about
+ * 1 ms of the device's FP64 rate. */
+#define FMM_SERVER_LARGE_FLOPS 6.0e10
+/* arena_bytes = 0: the arena takes the device's free memory at creation less
+ * this reserve (bytes) for the callers' operands and outputs. */
+#define FMM_SERVER_RESERVE_BYTES (16ull << 30)
+
 typedef struct {
-    size_t arena_bytes;  /* device bytes for workspaces and tables (admission budget) */
+    size_t arena_bytes;  /* device bytes for workspaces and tables (admission budget);
+                            0: all free device memory less FMM_SERVER_RESERVE_BYTES */
     int max_batch;       /* requests per batch, 1..64 (leaves of up to 8 share a launch) */
-    int max_inflight;    /* batches enqueued and not finished, >= 1 */
+    int max_inflight;    /* batches enqueued and not finished per stream, >= 1 */
     int fuse_levels;     /* as fmm_plan_options_t */
     int use_graph;       /* non-zero: each batch's launches are recorded into a HIP graph
                             (kernel nodes only), instantiated once and launched as one
@@ -342,6 +376,10 @@ typedef struct {
     double max_error[3]; /* per dtype (index = fmm_dtype): error budget of the automatic
                             choice for requests without a named plan, as
                             fmm_plan_options_t::max_error (0: default, < 0: no limit) */
+    int num_streams;     /* 0 or 1: one stream; 2..4: large requests on stream 0, the rest
+                            on the others (see above) */
+    double large_flops;  /* 2mkn at or above which a request is large (0: the default
+                            FMM_SERVER_LARGE_FLOPS); used with num_streams >= 2 */
 } fmm_server_options_t;
 
 typedef struct {
@@ -353,8 +391,8 @@ typedef struct {
     const void *B; int64_t ldb;
     void *C; int64_t ldc;
     void *user;          /* returned with the completion */
-    int wait_stream;     /* non-zero: the batch that runs the request first waits, on the
-                            server's stream, for the work enqueued on `stream` before the
+    int wait_stream;     /* non-zero: the batch that runs the request first waits, on its
+                            server stream, for the work enqueued on `stream` before the
                             submit (an event recorded there by fmm_server_submit), e.g. the
                             kernels that write A and B or that still use C's memory */
     void *stream;        /* hipStream_t for wait_stream (NULL: the null stream) */
@@ -370,12 +408,17 @@ typedef struct {
     int batch_size;
     char alg[80];
     int levels;
+    int lane;            /* the server stream its batch ran on (-1: not run) */
 } fmm_completion_t;
 
 /* Creates a server on the current device; allocates the arena there.  stream
- * NULL: the server creates its own stream.  FMM_ENOMEM when the arena cannot
- * be allocated. */
+ * non-NULL: the server's stream 0 (the others, if any, it creates); NULL: it
+ * creates all of them.  FMM_ENOMEM when the arena cannot be allocated;
+ * FMM_EINVAL for options out of range. */
 fmm_status fmm_server_create(fmm_server_t *out, const fmm_server_options_t *opts, void *stream);
+
+/* The arena's size in bytes (as resolved when arena_bytes was 0); 0 for NULL. */
+size_t fmm_server_arena_bytes(fmm_server_t s);
 
 /* Queues a request; *id is its sequence number.  The request is validated on
  * the host as fmm_multiply validates its arguments (sizes, dtype, NULL

@@ -50,13 +50,13 @@ class _Info(ctypes.Structure):
                 ("leaf_flops", ctypes.c_double), ("classical_flops", ctypes.c_double),
                 ("add_bytes", ctypes.c_double), ("gemm_min_bytes", ctypes.c_double),
                 ("fuse_levels", ctypes.c_int), ("alg", ctypes.c_char * 80), ("leaf_tile", ctypes.c_int),
-                ("pair_form", ctypes.c_int), ("error_bound", ctypes.c_double)]
+                ("pair_form", ctypes.c_int), ("error_bound", ctypes.c_double), ("leaf_form", ctypes.c_int)]
 
 
 class _Options(ctypes.Structure):
     _fields_ = [("fuse_levels", ctypes.c_int), ("host_only", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("defer_device_memory", ctypes.c_int),
-                ("leaf_tile", ctypes.c_int), ("max_error", ctypes.c_double)]
+                ("leaf_tile", ctypes.c_int), ("max_error", ctypes.c_double), ("leaf_form", ctypes.c_int)]
 
 
 class _Candidate(ctypes.Structure):
@@ -68,7 +68,8 @@ class _Candidate(ctypes.Structure):
 class _ServerOptions(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int),
                 ("max_inflight", ctypes.c_int), ("fuse_levels", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("max_error", ctypes.c_double * 3)]
+                ("max_error", ctypes.c_double * 3), ("num_streams", ctypes.c_int),
+                ("large_flops", ctypes.c_double)]
 
 
 class _Request(ctypes.Structure):
@@ -83,7 +84,7 @@ class _Completion(ctypes.Structure):
     _fields_ = [("id", ctypes.c_int64), ("user", ctypes.c_void_p), ("status", ctypes.c_int),
                 ("submit_ms", ctypes.c_double), ("launch_ms", ctypes.c_double),
                 ("done_ms", ctypes.c_double), ("batch_size", ctypes.c_int),
-                ("alg", ctypes.c_char * 80), ("levels", ctypes.c_int)]
+                ("alg", ctypes.c_char * 80), ("levels", ctypes.c_int), ("lane", ctypes.c_int)]
 
 
 def _load():
@@ -118,6 +119,7 @@ def _load():
         "fmm_server_submit": ([P, ctypes.POINTER(_Request), ctypes.POINTER(i64)], i32),
         "fmm_server_progress": ([P, i32, ctypes.POINTER(_Completion), i32, ctypes.POINTER(i32)], i32),
         "fmm_server_pending": ([P], i64),
+        "fmm_server_arena_bytes": ([P], ctypes.c_size_t),
         "fmm_server_destroy": ([P], i32),
         "fmm_run_stage": ([P, i32, vp, i64, vp, i64, vp, i64, vp], i32),
         "fmm_plan_operand": ([P, i32, i64, ctypes.POINTER(i32), ctypes.POINTER(i64),
@@ -189,11 +191,11 @@ class Plan:
     (``fmm_plan_host``) can be inspected but not run."""
 
     def __init__(self, alg, m, k, n, levels, dtype=F64, host_only=False, fuse_levels=0,
-                 use_graph=False, defer_device_memory=False, leaf_tile=0, max_error=0.0):
+                 use_graph=False, defer_device_memory=False, leaf_tile=0, max_error=0.0, leaf_form=0):
         self._p = ctypes.c_void_p()
         self.dtype = _dtype_code(dtype)
         opts = _Options(int(fuse_levels), 1 if host_only else 0, 1 if use_graph else 0,
-                        1 if defer_device_memory else 0, int(leaf_tile), float(max_error))
+                        1 if defer_device_memory else 0, int(leaf_tile), float(max_error), int(leaf_form))
         _check(_lib.fmm_plan_ex(ctypes.byref(self._p), alg.encode(), m, k, n, levels, self.dtype,
                                 ctypes.byref(opts)))
         self.m, self.k, self.n = m, k, n
@@ -363,10 +365,14 @@ class Server:
     tensors of every request alive until its completion has been returned."""
 
     def __init__(self, arena_bytes, max_batch=8, max_inflight=2, fuse_levels=0, stream=None, use_graph=False,
-                 max_error=(0.0, 0.0, 0.0)):
+                 max_error=(0.0, 0.0, 0.0), num_streams=1, large_flops=0.0):
+        """arena_bytes 0: the device's free memory less a reserve.  num_streams
+        2-4: large requests (2mkn >= large_flops, 0 = the library default) run
+        one per batch on stream 0, the rest on the other streams."""
         self._s = ctypes.c_void_p()
         opts = _ServerOptions(int(arena_bytes), int(max_batch), int(max_inflight), int(fuse_levels),
-                              1 if use_graph else 0, (ctypes.c_double * 3)(*[float(x) for x in max_error]))
+                              1 if use_graph else 0, (ctypes.c_double * 3)(*[float(x) for x in max_error]),
+                              int(num_streams), float(large_flops))
         sp = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
         _check(_lib.fmm_server_create(ctypes.byref(self._s), ctypes.byref(opts), sp))
         self._live = {}
@@ -410,6 +416,10 @@ class Server:
     @property
     def pending(self):
         return int(_lib.fmm_server_pending(self._s))
+
+    @property
+    def arena_bytes(self):
+        return int(_lib.fmm_server_arena_bytes(self._s))
 
     def close(self):
         if self._s:

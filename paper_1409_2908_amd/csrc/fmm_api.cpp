@@ -180,6 +180,7 @@ hipError_t run_leaf(const fmm::Plan& P, const fmm::Bases& b, hipStream_t s) {
   std::memset(&a, 0, sizeof(a));
   append_leaf(a, P, b, 0);
   a.tile = P.leaf_tile;
+  a.form_terms = P.leaf_form;
   return fmm::launch_gemm(a, P.dtype, num_cus(P.device), s);
 }
 
@@ -211,6 +212,14 @@ hipError_t run_stage(const fmm::Plan& P, int stage, const fmm::Bases& b, hipStre
     case FMM_STAGE_COMBINE: return run_combine(P, b, s);
   }
   return hipErrorInvalidValue;
+}
+
+// A stage as a multiply runs it: plans that form their leaf operands inside
+// the leaf GEMM skip the formation stages (fmm_run_stage still runs them, so
+// the formed operands can be inspected).
+hipError_t run_multiply_stage(const fmm::Plan& P, int stage, const fmm::Bases& b, hipStream_t s) {
+  if (P.leaf_form && (stage == FMM_STAGE_FORM_S || stage == FMM_STAGE_FORM_T)) return hipSuccess;
+  return run_stage(P, stage, b, s);
 }
 
 constexpr size_t kTableAlign = 256;
@@ -246,7 +255,7 @@ fmm_status capture_graph(fmm::Plan& P, const fmm::Bases& b) {
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
   hipError_t le = hipSuccess;
-  for (int stage = 0; stage < FMM_NUM_STAGES && le == hipSuccess; ++stage) le = run_stage(P, stage, b, cs);
+  for (int stage = 0; stage < FMM_NUM_STAGES && le == hipSuccess; ++stage) le = run_multiply_stage(P, stage, b, cs);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(cs, &g);
   if (le != hipSuccess || e != hipSuccess) {
@@ -305,7 +314,7 @@ fmm_status scratch_ptr(int dev, void** out) {
 
 fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
                        int dtype, int fuse, bool device, bool defer = false, bool graph = false,
-                       int leaf_tile = 0, double max_error = 0) {
+                       int leaf_tile = 0, double max_error = 0, int leaf_form = 0) {
   if (!out) return fail(FMM_EINVAL, "out is NULL");
   *out = nullptr;
   if (leaf_tile != 0 && leaf_tile != 64 && leaf_tile != 128 && !(leaf_tile == 256 && dtype == FMM_F32_BF16X3))
@@ -334,7 +343,7 @@ fmm_status plan_common(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
   fmm_plan_s* h = new (std::nothrow) fmm_plan_s();
   if (!h) return fail(FMM_ENOMEM, "host allocation failed");
   int code = 0;
-  std::string err = fmm::make_plan(h->P, alg, m, k, n, levels, dtype, fuse, &code);
+  std::string err = fmm::make_plan(h->P, alg, m, k, n, levels, dtype, fuse, &code, leaf_form);
   if (!err.empty()) {
     delete h;
     return fail((fmm_status)code, err);
@@ -437,7 +446,9 @@ fmm_status fmm_plan_ex(fmm_plan_t* out, const char* alg, int64_t m, int64_t k, i
   const bool graph = opts && opts->use_graph;
   const int tile = opts ? opts->leaf_tile : 0;
   const double max_error = opts ? opts->max_error : 0;
-  return plan_common(out, alg, m, k, n, levels, dtype, fuse, !host_only, defer, graph, tile, max_error);
+  const int leaf_form = opts ? opts->leaf_form : 0;
+  return plan_common(out, alg, m, k, n, levels, dtype, fuse, !host_only, defer, graph, tile, max_error,
+                     leaf_form);
 }
 
 size_t fmm_plan_device_bytes(fmm_plan_t p) {
@@ -510,7 +521,7 @@ fmm_status fmm_multiply(fmm_plan_t p, const void* A, int64_t lda, const void* B,
       hipError_t e = hipEventRecord((hipEvent_t)P.events[slot + stage], s);
       if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
-    hipError_t e = run_stage(P, stage, b, s);
+    hipError_t e = run_multiply_stage(P, stage, b, s);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
   }
   if (P.timing_slots) {
@@ -550,7 +561,7 @@ fmm_status fmm_multiply_noalloc(fmm_plan_t p, const void* A, int64_t lda, const 
   P.dev_table = (char*)mem + table_offset(P);
   e = hipMemcpyAsync(P.dev_table, P.table.data(), P.table_bytes, hipMemcpyHostToDevice, s);
   const fmm::Bases b = make_bases(P, A, lda, B, ldb, C, ldc);
-  for (int stage = 0; stage < FMM_NUM_STAGES && e == hipSuccess; ++stage) e = run_stage(P, stage, b, s);
+  for (int stage = 0; stage < FMM_NUM_STAGES && e == hipSuccess; ++stage) e = run_multiply_stage(P, stage, b, s);
   P.ws = ws0;
   P.dev_table = tab0;
   return e == hipSuccess ? FMM_OK : hip_fail(e, "no-allocation multiply");
@@ -581,15 +592,19 @@ fmm_status fmm_multiply_batched(const fmm_plan_t* plans, const void* const* A, c
   hipError_t e = hipSuccess;
   for (int stage : {FMM_STAGE_FORM_S, FMM_STAGE_FORM_T})
     for (int i : live)
-      if ((e = run_stage(plans[i]->P, stage, bases[i], s)) != hipSuccess) return hip_fail(e, "kernel launch");
-  // Leaves of all requests of one dtype share grouped launches, as many plans
-  // per launch as the argument block holds.
-  for (int dtype = 0; dtype <= 2; ++dtype) {
+      if ((e = run_multiply_stage(plans[i]->P, stage, bases[i], s)) != hipSuccess)
+        return hip_fail(e, "kernel launch");
+  // Leaves of all requests of one dtype (and one way of staging operands)
+  // share grouped launches, as many plans per launch as the argument block
+  // holds.
+  for (int key = 0; key < 3 * 2; ++key) {
+    const int dtype = key / 2, form = (key % 2) * fmm::kMaxLeafTerms;  // plain, or forming, operands
     fmm::GemmArgs a;
     std::memset(&a, 0, sizeof(a));
     int slots = 0;
     auto flush = [&]() -> hipError_t {
       hipError_t fe = hipSuccess;
+      a.form_terms = form;
       if (slots) fe = fmm::launch_gemm(a, dtype, num_cus(plans[live[0]]->P.device), s);
       std::memset(&a, 0, sizeof(a));
       slots = 0;
@@ -597,7 +612,7 @@ fmm_status fmm_multiply_batched(const fmm_plan_t* plans, const void* const* A, c
     };
     for (int i : live) {
       const fmm::Plan& P = plans[i]->P;
-      if (P.dtype != dtype || P.gemm_groups.empty()) continue;
+      if (P.dtype != dtype || P.leaf_form != form || P.gemm_groups.empty()) continue;
       if (slots == fmm::kMaxGemmSlots || a.ngroups + (int)P.gemm_groups.size() > fmm::kMaxGemmGroups)
         if ((e = flush()) != hipSuccess) return hip_fail(e, "kernel launch");
       append_leaf(a, P, bases[i], slots++);
@@ -706,6 +721,7 @@ fmm_status fmm_plan_info(fmm_plan_t p, fmm_plan_info_t* info) {
                 P.alg_id < 0 ? "classical" : mixed ? P.alg_name.c_str() : fmm::alg_info(P.alg_id).name);
   info->leaf_tile = P.leaf_tile;
   info->pair_form = P.pair_form ? 1 : 0;
+  info->leaf_form = P.leaf_form;
   info->error_bound = fmm::error_bound(P.levels > 0 ? P.lv_alg : std::vector<int>(), P.k, P.dtype);
   return FMM_OK;
 }

@@ -79,10 +79,21 @@ struct Mfma<float> {
 
 
 // BM x BN output tile per workgroup of 4 wavefronts (2 x 2): 128 x 128 (the
-// large-problem shape, two workgroups per CU) or 64 x 64 (for launches with
+// large-problem shape, two workgroups per CU), 64 x 64 (for launches with
 // fewer large tiles than compute units, where four times as many tiles keep
-// more of the chip busy).
-template <typename T, int BM, int BN>
+// more of the chip busy) or 32 x 32 (launches with at most half as many 64 x
+// 64 tiles as units).
+//
+// NT > 0 (plans with leaf-side formation): every problem's A and B tiles are
+// formed while they are staged, as sum_t coef_t * X_t over up to NT blocks
+// X_t of the operand (LeafTerms; views and peel strips have one term of
+// coefficient 1).  The loads of all terms are issued with the step's other
+// loads; the sums are taken in lstore, once they have landed, in the order
+// and precision of the formation pass (FP64, ascending block index, the first
+// term initialising, one rounding per add or subtract; then one rounding to
+// T), so the staged values, and the products, equal those of a plan that
+// writes S and T first, bit for bit.
+template <typename T, int BM, int BN, int NT>
 __global__ void __launch_bounds__(GNT) __attribute__((amdgpu_waves_per_eu(2, BM == 128 ? 2 : 8)))
 gemm_kernel(GemmArgs args) {
   const GemmArgs* ap = kernarg_args();
@@ -113,9 +124,24 @@ gemm_kernel(GemmArgs args) {
     T* C = (T*)slot_ptr(ap, job.slot, pr.c, &ldc) + pr.c.off;
     // Everything below is the same for the whole workgroup; saying so keeps
     // the buffer resources in scalar registers.
+    const T* A0 = A;
+    const T* B0 = B;
     A = uniform_ptr(A + (pr.a.row + job.tm * BM) * lda + pr.a.col);
     B = uniform_ptr(B + pr.b.row * ldb + pr.b.col + job.tn * BN);
     C = uniform_ptr(C + (pr.c.row + job.tm * BM) * ldc + pr.c.col + job.tn * BN);
+    // formed operands: the tile's origin in each term's block, and its coefficient
+    const T* At[NT > 0 ? NT : 1];
+    const T* Bt[NT > 0 ? NT : 1];
+    int ca[NT > 0 ? NT : 1], cb[NT > 0 ? NT : 1];
+    if constexpr (NT > 0) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        ca[t] = uniform_int(pr.fa.coef[t]);
+        cb[t] = uniform_int(pr.fb.coef[t]);
+        At[t] = uniform_ptr(A0 + (pr.a.row + pr.fa.drow[t] + job.tm * BM) * lda + pr.a.col + pr.fa.dcol[t]);
+        Bt[t] = uniform_ptr(B0 + (pr.b.row + pr.fb.drow[t]) * ldb + pr.b.col + pr.fb.dcol[t] + job.tn * BN);
+      }
+    }
     const int64_t mr = job.m - job.tm * BM, nr = job.n - job.tn * BN;
     const int mrem = uniform_int(mr < BM ? (int)mr : BM);
     const int nrem = uniform_int(nr < BN ? (int)nr : BN);
@@ -137,25 +163,67 @@ gemm_kernel(GemmArgs args) {
 #pragma unroll
       for (int j = 0; j < TJ; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-    T ra[EA], rb[EB];
+    constexpr int NTL = NT > 0 ? NT : 1;  // loads per staged element
+    T ra[NTL][EA], rb[NTL][EB];
     auto gload = [&](int64_t k0) {
-      const __amdgpu_buffer_rsrc_t sa = make_rsrc(A + k0);
-      const __amdgpu_buffer_rsrc_t sb = make_rsrc(B + k0 * (int64_t)ildb);
       // One branch-free path for full and partial K steps: a branch here would
       // merge the loaded registers and force a wait for the loads to land.
       const int kr = K - k0 < GBK ? (int)(K - k0) : GBK;
       const int av = ac < kr ? a_base : kInvalidOff;
       const int b_rows = (kr - br + RB - 1) / RB;
 #pragma unroll
-      for (int j = 0; j < EA; ++j) ra[j] = MF::load(sa, j < a_rows ? av : kInvalidOff, j * a_step);
+      for (int t = 0; t < NTL; ++t) {
+        // unused term slots (coefficient 0) read through the invalid offset
+        const T* a_src = NT > 0 ? At[t] : A;
+        const T* b_src = NT > 0 ? Bt[t] : B;
+        const bool a_on = NT == 0 || ca[t] != 0, b_on = NT == 0 || cb[t] != 0;
+        const __amdgpu_buffer_rsrc_t sa = make_rsrc(a_src + k0);
+        const __amdgpu_buffer_rsrc_t sb = make_rsrc(b_src + k0 * (int64_t)ildb);
 #pragma unroll
-      for (int j = 0; j < EB; ++j) rb[j] = MF::load(sb, j < b_rows ? b_base : kInvalidOff, j * b_step);
+        for (int j = 0; j < EA; ++j) ra[t][j] = MF::load(sa, a_on && j < a_rows ? av : kInvalidOff, j * a_step);
+#pragma unroll
+        for (int j = 0; j < EB; ++j)
+          rb[t][j] = MF::load(sb, b_on && j < b_rows ? b_base : kInvalidOff, j * b_step);
+      }
+    };
+    // sum_t c[t] * x[t] in FP64, ascending t, the first non-zero term
+    // initialising (c * x is exact for c = +-1, and a fused multiply-add then
+    // rounds exactly like the add or subtract of the formation pass)
+    auto chain = [&](const double* v, const int* c) -> T {
+      double acc = 0.0;
+      bool first = true;
+#pragma unroll
+      for (int t = 0; t < NTL; ++t) {
+        if (c[t] == 0) continue;
+        acc = first ? (double)c[t] * v[t] : __fma_rn((double)c[t], v[t], acc);
+        first = false;
+      }
+      return (T)acc;
+    };
+    auto form_a = [&](int j) -> T {
+      double v[NTL];
+#pragma unroll
+      for (int t = 0; t < NTL; ++t) v[t] = (double)ra[t][j];
+      return chain(v, ca);
+    };
+    auto form_b = [&](int j) -> T {
+      double v[NTL];
+#pragma unroll
+      for (int t = 0; t < NTL; ++t) v[t] = (double)rb[t][j];
+      return chain(v, cb);
     };
     auto lstore = [&](int buf) {
+      if constexpr (NT == 0) {
 #pragma unroll
-      for (int j = 0; j < EA; ++j) As[buf][ar + RA * j][ac] = ra[j];
+        for (int j = 0; j < EA; ++j) As[buf][ar + RA * j][ac] = ra[0][j];
 #pragma unroll
-      for (int j = 0; j < EB; ++j) Bs[buf][br + RB * j][bc] = rb[j];
+        for (int j = 0; j < EB; ++j) Bs[buf][br + RB * j][bc] = rb[0][j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < EA; ++j) As[buf][ar + RA * j][ac] = form_a(j);
+#pragma unroll
+        for (int j = 0; j < EB; ++j) Bs[buf][br + RB * j][bc] = form_b(j);
+      }
     };
 
     const int64_t nk = (K + GBK - 1) / GBK;
@@ -244,12 +312,24 @@ gemm_kernel(GemmArgs args) {
   }
 }
 
-template <typename T, int BM>
+// Persistent grids: as many workgroups as fit at once (each walks tiles with
+// a stride), or one per tile when there are fewer tiles.  (One workgroup per
+// tile throughout measured the same for the FP64 leaves and 7% slower for the
+// 256 x 256 BF16x3 leaves.)
+int64_t leaf_grid(int64_t resident, int64_t tiles) {
+  const int64_t want = (tiles + 7) / 8 * 8;
+  int64_t G = want < resident ? want : resident;
+  if (G < 8) G = 8;
+  return G / 8 * 8;
+}
+
+template <typename T, int BM, int NT>
 static int blocks_per_cu() {
   static std::atomic<int> cached{0};
   int b = cached.load(std::memory_order_relaxed);
   if (!b) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, gemm_kernel<T, BM, BM>, GNT, 0) != hipSuccess || b < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, gemm_kernel<T, BM, BM, NT>, GNT, 0) != hipSuccess ||
+        b < 1)
       b = 1;
     cached.store(b, std::memory_order_relaxed);
   }
@@ -266,7 +346,7 @@ static int pick_tile(const GemmArgs& a, int num_cus) {
   return use_small_tiles(a.total_tiles, num_cus) ? 64 : 128;
 }
 
-template <typename T, int BM>
+template <typename T, int BM, int NT>
 static hipError_t launch_tiles(const GemmArgs& a, int num_cus, hipStream_t s) {
   const GemmArgs* pa = &a;
   GemmArgs re;
@@ -283,21 +363,46 @@ static hipError_t launch_tiles(const GemmArgs& a, int num_cus, hipStream_t s) {
     re.total_tiles = tiles;
     pa = &re;
   }
-  int64_t G = (int64_t)blocks_per_cu<T, BM>() * num_cus;
-  const int64_t want = (pa->total_tiles + 7) / 8 * 8;
-  if (want < G) G = want;
-  if (G < 8) G = 8;
-  G = G / 8 * 8;
-  hipLaunchKernelGGL((gemm_kernel<T, BM, BM>), dim3((unsigned)G), dim3(GNT), 0, s, *pa);
+  const int64_t G = leaf_grid((int64_t)blocks_per_cu<T, BM, NT>() * num_cus, pa->total_tiles);
+  hipLaunchKernelGGL((gemm_kernel<T, BM, BM, NT>), dim3((unsigned)G), dim3(GNT), 0, s, *pa);
   return hipGetLastError();
+}
+
+// Launches that form their operands run 64 x 64 tiles (the plans that use
+// them have small leaf launches, and the 128 x 128 tile's registers could not
+// hold the terms' loads in flight).
+// 64 x 64 tiles of a launch.
+static int64_t tiles64(const GemmArgs& a) {
+  int64_t t = 0;
+  for (int i = 0; i < a.ngroups; ++i) t += ((a.groups[i].m + 63) / 64) * ((a.groups[i].n + 63) / 64) * a.groups[i].count;
+  return t;
+}
+
+// Launches with so few 64 x 64 tiles that most compute units would idle
+// (at most half as many as units) run 32 x 32 tiles: a tile's time is then
+// bound by its one compute unit's matrix and load rate, and four times as many
+// tiles spread the product over four times as many units.  Every tile edge
+// accumulates each output element over the same K steps in the same order.
+template <typename T, int NT>
+static hipError_t launch_typed(const GemmArgs& a, int num_cus, hipStream_t s) {
+  if (a.tile == 0 && 2 * tiles64(a) <= num_cus) return launch_tiles<T, 32, NT>(a, num_cus, s);
+  if constexpr (NT > 0) return launch_tiles<T, 64, NT>(a, num_cus, s);
+  else
+    return pick_tile(a, num_cus) == 64 ? launch_tiles<T, 64, 0>(a, num_cus, s) : launch_tiles<T, 128, 0>(a, num_cus, s);
+}
+
+template <typename T>
+static hipError_t launch_forms(const GemmArgs& a, int num_cus, hipStream_t s) {
+  if (a.form_terms == 0) return launch_typed<T, 0>(a, num_cus, s);
+  if (a.form_terms == kMaxLeafTerms) return launch_typed<T, kMaxLeafTerms>(a, num_cus, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_gemm(const GemmArgs& a, int dtype, int num_cus, hipStream_t s) {
   if (a.total_tiles <= 0) return hipSuccess;
-  if (dtype == 2) return launch_gemm_bf16x3(a, num_cus, s);
-  const bool small = pick_tile(a, num_cus) == 64;
-  if (dtype == 0) return small ? launch_tiles<double, 64>(a, num_cus, s) : launch_tiles<double, 128>(a, num_cus, s);
-  if (dtype == 1) return small ? launch_tiles<float, 64>(a, num_cus, s) : launch_tiles<float, 128>(a, num_cus, s);
+  if (dtype == 2) return a.form_terms ? hipErrorInvalidValue : launch_gemm_bf16x3(a, num_cus, s);
+  if (dtype == 0) return launch_forms<double>(a, num_cus, s);
+  if (dtype == 1) return launch_forms<float>(a, num_cus, s);
   return hipErrorInvalidValue;
 }
 

@@ -809,11 +809,7 @@ static hipError_t launch_bf16x3_tiles(const GemmArgs& a, int num_cus, hipStream_
       per_cu = 1;
     cached.store(per_cu, std::memory_order_relaxed);
   }
-  int64_t G = (int64_t)per_cu * num_cus;
-  const int64_t want = (pa->total_tiles + 7) / 8 * 8;
-  if (want < G) G = want;
-  if (G < 8) G = 8;
-  G = G / 8 * 8;
+  const int64_t G = leaf_grid((int64_t)per_cu * num_cus, pa->total_tiles);
   hipLaunchKernelGGL(gemm_bf16x3_kernel<TM>, dim3((unsigned)G), dim3(XNT), 0, s, *pa);
   return hipGetLastError();
 }
@@ -843,11 +839,7 @@ static hipError_t launch_bf16x3_big(const GemmArgs& a, int num_cus, hipStream_t 
       per_cu = 1;
     cached.store(per_cu, std::memory_order_relaxed);
   }
-  int64_t G = (int64_t)per_cu * num_cus;
-  const int64_t want = (re.total_tiles + 7) / 8 * 8;
-  if (want < G) G = want;
-  if (G < 8) G = 8;
-  G = G / 8 * 8;
+  const int64_t G = leaf_grid((int64_t)per_cu * num_cus, re.total_tiles);
   hipLaunchKernelGGL(gemm_bf16x3_big_kernel, dim3((unsigned)G), dim3(XNT), 0, s, re);
   return hipGetLastError();
 }

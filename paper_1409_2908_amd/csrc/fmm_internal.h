@@ -84,10 +84,23 @@ struct CombinePass {
   size_t dev_in = 0, dev_out = 0;
 };
 
+// A leaf operand formed while the GEMM stages it (plans with leaf_form): the
+// sum over n terms of coef * (alpha times the block at (row + drow, col +
+// dcol) of the operand's view), as the formation pass would have written it.
+// Unused terms have coef 0.
+constexpr int kMaxLeafTerms = 2;
+struct LeafTerms {
+  int32_t n;
+  int32_t coef[kMaxLeafTerms];
+  int32_t pad_;
+  int64_t drow[kMaxLeafTerms], dcol[kMaxLeafTerms];
+};
+
 struct GemmProb {
   Ref a, b, c;
   double alpha;
   double pad;
+  LeafTerms fa, fb;  // read only by the forming kernels (GemmArgs::form_terms > 0)
 };
 
 // Problems of identical shape; tiles of all groups form one flat index space.
@@ -113,7 +126,7 @@ struct GemmArgs {
   int ngroups;
   int elt;
   int tile;  // output tile edge of the FP64 / FP32 kernel: 64, 128, or 0 (chosen at launch)
-  int pad_;
+  int form_terms;  // 0: plain operands; kMaxLeafTerms: every problem forms A and B from LeafTerms
   int64_t total_tiles;
   GemmGroup groups[kMaxGemmGroups];
 };
@@ -180,6 +193,8 @@ struct Plan {
   bool external = false;        // device memory bound by the caller (not owned)
   bool use_graph = false;       // replay the stages as a captured HIP graph
   bool pair_form = false;       // S and T formed by one launch (small one-level plans)
+  int leaf_form = 0;            // > 0: the leaf GEMM forms S and T while staging them, with
+                                // this many term slots (kMaxLeafTerms); multiply skips the passes
   int leaf_tile = 0;            // FP64 / FP32 leaf tile edge: 64, 128, or 0 (chosen per launch)
   void* graph_exec = nullptr;   // hipGraphExec_t of the last capture
   void* cap_stream = nullptr;   // private stream the capture is recorded on
@@ -191,7 +206,7 @@ struct Plan {
 // Plans on the host only; fills every field above except the device side.
 // Returns an empty string on success, else the error message (and sets *code).
 std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
-                      int dtype, int fuse, int* code);
+                      int dtype, int fuse, int* code, int leaf_form = 0);
 
 int find_algorithm(const char* name);  // -1 for "classical", -2 unknown
 
@@ -213,13 +228,20 @@ struct PlanSummary {
   size_t ws_bytes = 0;
   int form_passes = 0, comb_passes = 0;
   bool pair_form = false;  // S and T formed by one launch (Plan::pair_form)
+  int leaf_form = 0;       // S and T formed inside the leaf GEMM (Plan::leaf_form)
 };
+
+// Plans whose leaf launch has at most this many 128 x 128 tiles form their
+// leaf operands inside the leaf GEMM by default (Plan::leaf_form): below it
+// the leaves cannot fill the device, so a separate formation launch, and the
+// idle gap before the leaves, costs more than the leaves' extra operand reads.
+constexpr int64_t kLeafFormMaxTiles = 256;
 
 // Plans of one level whose S and T passes together cover at most this many
 // output positions form both in one launch (Plan::pair_form).
 constexpr int64_t kPairFormMaxPositions = int64_t(1) << 20;
 std::string summarize_plan(PlanSummary& S, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
-                           int dtype, int fuse);
+                           int dtype, int fuse, int leaf_form = 0);
 
 // Sets the calling thread's error message (fmm_last_error); returns code.
 int set_error(int code, const std::string& msg);

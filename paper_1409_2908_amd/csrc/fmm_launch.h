@@ -18,5 +18,8 @@ hipError_t launch_combine(int alg, const CombineArgs& a, int lv, int ngroups, hi
 // dtype (0: FP64 MFMA, 1: FP32 MFMA, 2: BF16x3 MFMA) select the kernel.
 hipError_t launch_gemm(const GemmArgs& a, int dtype, int num_cus, hipStream_t s);
 hipError_t launch_gemm_bf16x3(const GemmArgs& a, int num_cus, hipStream_t s);
+// Workgroups of a grouped leaf launch over `tiles` tiles, `resident` of
+// which fit on the device at once (a multiple of 8, at least 8).
+int64_t leaf_grid(int64_t resident, int64_t tiles);
 
 }  // namespace fmm

@@ -72,6 +72,31 @@ int resolve_fuse(int requested, int R, int dtype, const std::vector<int>& ids) {
   return (dtype == 2 && R > 8) ? 1 : 2;  // dtype 2: FP32 inputs with BF16x3 leaves
 }
 
+// Term slots a plan needs to form its leaf operands inside the leaf GEMM
+// (kMaxLeafTerms), or 0 when it cannot: one level, FP64 / FP32 (the BF16x3
+// leaves read split operands), every S and T column with at most
+// kMaxLeafTerms non-zeros (Strassen and its direct sums), all of them +-1 (a
+// multiply-add then rounds like the pass's add or subtract).
+int leaf_form_terms(const std::vector<int>& ids, int levels, int dtype) {
+  if (levels != 1 || dtype == 2 || ids.size() != 1) return 0;
+  const AlgInfo& A = alg_info(ids[0]);
+  int most = 0;
+  for (int side = 0; side < 2; ++side) {
+    const signed char* X = side == 0 ? A.U : A.V;
+    const int rows = side == 0 ? A.M * A.K : A.K * A.N;
+    for (int r = 0; r < A.R; ++r) {
+      int nz = 0;
+      for (int i = 0; i < rows; ++i) {
+        const int c = X[i * A.R + r];
+        if (c != 0 && c != 1 && c != -1) return 0;
+        nz += c != 0;
+      }
+      most = nz > most ? nz : most;
+    }
+  }
+  return most <= kMaxLeafTerms ? kMaxLeafTerms : 0;
+}
+
 // Splits L levels into passes of at most `fuse` levels.  Operand formation
 // runs top-down and keeps the fused pass at the bottom (fewest bytes: the
 // R^L outputs are written once); the combination runs bottom-up with the
@@ -298,7 +323,7 @@ void summarize_side(const std::vector<int>& ids, int side, int fuse, int dtype, 
 }  // namespace
 
 std::string summarize_plan(PlanSummary& S, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
-                           int dtype, int fuse) {
+                           int dtype, int fuse, int leaf_form) {
   S = PlanSummary();
   if (m < 0 || k < 0 || n < 0) return "sizes must be non-negative";
   if (levels < 0 || levels > 6) return "levels must be in [0, 6]";
@@ -361,6 +386,10 @@ std::string summarize_plan(PlanSummary& S, const char* alg, int64_t m, int64_t k
     // the condition make_plan applies: one unsplit pass per side of one level
     S.pair_form = L == 1 && dtype != 2 && S.form_passes == 2 &&
                   (m0 / fm) * (k0 / fk) + (k0 / fk) * (n0 / fn) <= kPairFormMaxPositions;
+    const int nt = leaf_form_terms(ids, L, dtype);
+    const int64_t leaf_tiles = ((ml + kTileM - 1) / kTileM) * ((nl + kTileN - 1) / kTileN) * nleaves;
+    S.leaf_form = (leaf_form == 2 || (leaf_form == 0 && leaf_tiles <= kLeafFormMaxTiles)) ? nt : 0;
+    if (leaf_form == 2 && nt == 0) return "leaf_form 2 needs a one-level FP64 / FP32 plan";
   }
   for (GemmGroup& g : S.groups) {
     g.tiles_m = (g.m + kTileM - 1) / kTileM;
@@ -423,12 +452,13 @@ int parse_levels(const char* alg, int levels, std::vector<int>* ids, std::string
 }
 
 std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n, int levels,
-                      int dtype, int fuse, int* code) {
+                      int dtype, int fuse, int* code, int leaf_form) {
   *code = 1;  // FMM_EINVAL
   if (m < 0 || k < 0 || n < 0) return "sizes must be non-negative";
   if (levels < 0 || levels > 6) return "levels must be in [0, 6]";
   if (dtype < 0 || dtype > 2) return "unknown dtype";
   if (fuse < 0 || fuse > 2) return "fuse must be 0 (default), 1 or 2";
+  if (leaf_form < 0 || leaf_form > 2) return "leaf_form must be 0 (default), 1 or 2";
   std::vector<int> ids;
   std::string perr;
   const int pr = parse_levels(alg, levels, &ids, &perr);
@@ -623,6 +653,54 @@ std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n,
   P.gemm_tiles = tiles;
   P.add_bytes = add_bytes;
   P.ws_bytes = ws.used;
+  // Leaf operands formed inside the leaf GEMM: every problem's A and B become
+  // term lists (leaf r: the non-zeros of column r of U and V over the blocks
+  // of A and B, in ascending block order, the pass's chain order; views and
+  // peel strips: one term).  The S and T passes stay in the plan (the
+  // FMM_STAGE_FORM_* stages still write them) but fmm_multiply skips them.
+  {
+    const int nt = P.levels > 0 ? leaf_form_terms(P.lv_alg, P.levels, dtype) : 0;
+    if (leaf_form == 2 && nt == 0)
+      return "leaf_form 2 needs a one-level FP64 / FP32 plan whose S and T columns have at most " +
+             std::to_string(kMaxLeafTerms) + " non-zeros, each +-1";
+    const bool small = !P.gemm_groups.empty() &&
+                       P.gemm_groups[0].tiles_m * P.gemm_groups[0].tiles_n * P.gemm_groups[0].count <=
+                           kLeafFormMaxTiles;
+    P.leaf_form = (leaf_form == 2 || (leaf_form == 0 && small)) ? nt : 0;
+  }
+  if (P.leaf_form) {
+    const AlgInfo& A = alg_info(P.lv_alg[0]);
+    auto one = [](LeafTerms& t) {
+      std::memset(&t, 0, sizeof(t));
+      t.n = 1;
+      t.coef[0] = 1;
+    };
+    for (GemmProb& pr : P.gemm_probs) {
+      one(pr.fa);
+      one(pr.fb);
+    }
+    for (int r = 0; r < A.R; ++r) {
+      GemmProb& pr = P.gemm_probs[r];
+      for (int side = 0; side < 2; ++side) {
+        Ref& op = side == 0 ? pr.a : pr.b;
+        if (op.buf != BUF_WS) continue;  // a view: one term
+        LeafTerms& t = side == 0 ? pr.fa : pr.fb;
+        const signed char* X = side == 0 ? A.U : A.V;
+        const int BC = side == 0 ? A.K : A.N, rows = side == 0 ? A.M * A.K : A.K * A.N;
+        const int64_t bh = side == 0 ? P.ml : P.kl, bw = side == 0 ? P.kl : P.nl;
+        std::memset(&t, 0, sizeof(t));
+        for (int i = 0; i < rows; ++i) {
+          const int c = X[i * A.R + r];
+          if (c == 0) continue;
+          t.coef[t.n] = c;
+          t.drow[t.n] = (int64_t)(i / BC) * bh;
+          t.dcol[t.n] = (int64_t)(i % BC) * bw;
+          ++t.n;
+        }
+        op = Ref{side == 0 ? BUF_A : BUF_B, P.elt, 0, 0, 0, 0, 1.0};
+      }
+    }
+  }
   // Small one-level plans form S and T in one launch: between two dependent
   // launches the queue idles about as long as one such pass takes.
   if (P.s_passes.size() == 1 && P.t_passes.size() == 1) {

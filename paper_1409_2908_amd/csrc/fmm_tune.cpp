@@ -44,6 +44,9 @@ constexpr int kCUs = kSlots / 2;
 constexpr int kSlotsSmall = 4 * kCUs;  // resident 64 x 64 leaf workgroups (4 per compute unit)
 // full-occupancy rate of the 64 x 64 tile relative to the 128 x 128 one
 constexpr double kSmallF64 = 0.93, kSmallF32 = 0.74, kSmallBf16x3 = 0.68;
+// rate of a 32 x 32 tile alone on its compute unit relative to the 128 x 128
+// rate (512^3 FP64: 256 such tiles in 15.6 us; taken for FP32 as well)
+constexpr double kTiny = 0.28;
 constexpr int64_t kMaxLeaves = 60000;  // candidates with more leaves are not offered
 
 // Rate of group g of a plan: on the BF16x3 path the leaf group (the first
@@ -99,6 +102,21 @@ void predict(const PlanSummary& P, int dtype, Candidate& c) {
         w_r = std::max(w_r, (double)g.k + kFix);
       }
     if (tiles_r > 0) leaf_s += waves_time(units_r, w_r, tiles_r, kSlots / kCUs, (double)kTileM, kRateBf16x3) + kLaunch;
+  } else if (tiles > 0 && dtype != 2 && [&] {
+               double t64 = 0;
+               for (const GemmGroup& g : P.groups) t64 += (double)((g.m + 63) / 64) * ((g.n + 63) / 64) * g.count;
+               return 2.0 * t64 <= kCUs;
+             }()) {
+    // the launch runs 32 x 32 tiles (launch_gemm: at most half as many 64 x 64
+    // tiles as compute units)
+    double units32 = 0, tiles32 = 0;
+    for (size_t i = 0; i < P.groups.size(); ++i) {
+      const GemmGroup& g = P.groups[i];
+      const double t = (double)((g.m + 31) / 32) * ((g.n + 31) / 32) * g.count;
+      units32 += t * ((double)g.k + kFix) * ref / rate(dtype, i == 0 && P.levels > 0);
+      tiles32 += t;
+    }
+    leaf_s = waves_time(units32, wmax, tiles32, kSlotsSmall / kCUs, 32, ref * kTiny);
   } else if (tiles > 0 && use_small_tiles((int64_t)tiles, kCUs, dtype == 2)) {
     // the launch runs 64 x 64 tiles (units weighted by each group's rate,
     // as for the large tiles)
@@ -115,8 +133,8 @@ void predict(const PlanSummary& P, int dtype, Candidate& c) {
     leaf_s = waves_time(units, wmax, tiles, kSlots / kCUs, (double)kTileM, ref);
   }
   const double add_s = P.add_bytes / kAddBw;
-  // a pair-formed plan forms S and T in one launch
-  const double launches = 1.0 + P.form_passes + P.comb_passes - (P.pair_form ? 1 : 0);
+  // a pair-formed plan forms S and T in one launch, a leaf-formed one in none
+  const double launches = 1.0 + P.comb_passes + (P.leaf_form ? 0 : P.form_passes - (P.pair_form ? 1 : 0));
   c.leaf_ms = leaf_s * 1e3;
   c.add_ms = add_s * 1e3;
   c.model_ms = (leaf_s + add_s + launches * kLaunch) * 1e3;

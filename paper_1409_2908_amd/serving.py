@@ -19,6 +19,9 @@ import numpy as np
 
 from . import F32_BF16X3, F64, Plan, Server
 
+# the library's default large-request threshold (FMM_SERVER_LARGE_FLOPS, 2mkn)
+LARGE_FLOPS = 6.0e10
+
 __all__ = ["make_requests", "Pools", "run_stream", "percentile", "check_alone"]
 
 
@@ -69,7 +72,7 @@ def percentile(x, q):
 
 
 def run_stream(requests, arrivals_ms, pools, arena_bytes, max_batch=8, max_inflight=2, alg=None,
-               levels=-1, keep=None, max_outstanding=64, use_graph=False):
+               levels=-1, keep=None, max_outstanding=64, use_graph=False, num_streams=1, large_flops=0.0):
     """Replay the stream in real time through a server.  `alg`/`levels` apply
     to every request (None / -1: the library's per-shape choice).  At most
     `max_outstanding` requests are submitted and unfinished at once (their
@@ -85,7 +88,10 @@ def run_stream(requests, arrivals_ms, pools, arena_bytes, max_batch=8, max_infli
     meta = {}
     batches = []
     algs = {}
-    srv = Server(arena_bytes, max_batch=max_batch, max_inflight=max_inflight, use_graph=use_graph)
+    srv = Server(arena_bytes, max_batch=max_batch, max_inflight=max_inflight, use_graph=use_graph,
+                 num_streams=num_streams, large_flops=large_flops)
+    arena_gb = srv.arena_bytes / 1e9
+    lanes = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     i = done = 0
@@ -99,6 +105,7 @@ def run_stream(requests, arrivals_ms, pools, arena_bytes, max_batch=8, max_infli
             # host delay from arrival to submit, plus the server's submit -> done
             lat[idx] = (sub_wall - arr_ms) + (c["done_ms"] - c["submit_ms"])
             batches.append(c["batch_size"])
+            lanes[c["lane"]] = lanes.get(c["lane"], 0) + 1
             key = f"{c['alg']}/L{c['levels']}"
             algs[key] = algs.get(key, 0) + 1
             if idx in kept:
@@ -131,6 +138,9 @@ def run_stream(requests, arrivals_ms, pools, arena_bytes, max_batch=8, max_infli
             collect(srv.progress(wait=True))
     wall = time.perf_counter() - t0
     srv.close()
+    # the server's large-request class (the library default threshold for 0)
+    thr = large_flops or LARGE_FLOPS
+    small = np.array([2.0 * m * k * nn < thr for m, k, nn, _ in requests])
     return {
         "requests": n,
         "wall_s": wall,
@@ -138,7 +148,11 @@ def run_stream(requests, arrivals_ms, pools, arena_bytes, max_batch=8, max_infli
         "eff_tflops": flops / wall / 1e12,
         "p50_ms": percentile(lat, 50),
         "p99_ms": percentile(lat, 99),
+        "p99_ms_below_large": percentile(lat[small], 99) if small.any() else 0.0,
+        "p99_ms_large": percentile(lat[~small], 99) if (~small).any() else 0.0,
         "mean_batch": float(np.mean(batches)) if batches else 0.0,
+        "arena_gb": round(arena_gb, 1),
+        "requests_per_stream": {str(k): v for k, v in sorted(lanes.items())},
         "plans": dict(sorted(algs.items(), key=lambda kv: -kv[1])),
     }, kept
 

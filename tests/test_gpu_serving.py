@@ -128,6 +128,43 @@ def test_serving_workload_sizes_alone_vs_mix_and_oracle():
     torch.cuda.synchronize()
 
 
+def test_three_streams_classes_alone_vs_mix_and_oracle():
+    """Three server streams: every request of 2mkn >= the large threshold runs
+    alone in its batch on stream 0, every other request on streams 1-2; each
+    result is bitwise the same plan run alone and within its gate against the
+    binary64 oracle on sampled rows (the lanes share no device memory)."""
+    import torch
+    import paper_1409_2908_amd as F
+    from paper_1409_2908_amd import serving
+    n_req = 200
+    reqs = serving.make_requests(51, n_req)
+    pools = serving.Pools(8192, seed=11)
+    arr = serving.poisson_arrivals(53, n_req, 3000.0)
+    thr = 2.0 * 2048 ** 3
+    say(f"case serving three streams {n_req} requests")
+    stats, kept = serving.run_stream(reqs, arr, pools, arena_bytes=64 << 30, max_batch=8, max_inflight=2,
+                                     keep=set(range(n_req)), max_outstanding=32, num_streams=3,
+                                     large_flops=thr)
+    say(f"  {stats}")
+    assert stats["requests"] == n_req
+    n_large = 0
+    for idx, r in kept.items():
+        c = r["completion"]
+        m, k = r["A"].shape
+        n = r["B"].shape[1]
+        if 2.0 * m * k * n >= thr:
+            n_large += 1
+            assert c["lane"] == 0 and c["batch_size"] == 1, (idx, c)
+        else:
+            assert c["lane"] in (1, 2), (idx, c)
+    assert 0 < n_large < n_req
+    assert set(stats["requests_per_stream"]) == {"0", "1", "2"}
+    assert serving.check_alone(kept) == n_req
+    worst = _check_sampled_rows(F, kept, 300)
+    say(f"  oracle on sampled rows: worst relF / ratio to gate per dtype {worst}")
+    torch.cuda.synchronize()
+
+
 def test_invalid_request_is_refused_alone():
     """A request whose ldc is below n is refused at submit with its own
     status; the valid requests around it run and complete normally."""
@@ -155,13 +192,15 @@ def test_invalid_request_is_refused_alone():
         assert max(c["batch_size"] for c in got.values()) > 1
 
 
-def test_request_waits_for_its_stream():
+@pytest.mark.parametrize("num_streams", [1, 3])
+def test_request_waits_for_its_stream(num_streams):
     """Operands written on another stream by work that has not finished when
     the request is submitted: the batch waits for that stream, so the result
-    is that of the written operands."""
+    is that of the written operands (with one server stream and with three,
+    where the request runs on a small-request stream)."""
     import torch
     import paper_1409_2908_amd as F
-    say("case serving waits for the request's stream")
+    say(f"case serving waits for the request's stream, {num_streams} server streams")
     dev = torch.device("cuda")
     m, k, n = 1024, 1024, 1024
     srcA = torch.rand((m, k), dtype=torch.float64, device=dev)
@@ -172,7 +211,7 @@ def test_request_waits_for_its_stream():
     X = torch.rand((4096, 4096), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
     s1 = torch.cuda.Stream()
-    with F.Server(1 << 28, max_batch=4) as srv:
+    with F.Server(1 << 28, max_batch=4, num_streams=num_streams) as srv:
         with torch.cuda.stream(s1):
             for _ in range(40):  # about 50 ms of work ahead of the writes
                 Y = X @ X
@@ -183,6 +222,7 @@ def test_request_waits_for_its_stream():
         while not done:
             done = srv.progress(wait=True)
         assert done[0]["id"] == rid and done[0]["status"] == 0
+        assert done[0]["lane"] == (0 if num_streams == 1 else 1)
     torch.cuda.synchronize()
     del Y
     with F.Plan("strassen_222_7", m, k, n, 1) as p:

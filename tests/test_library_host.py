@@ -229,9 +229,12 @@ def test_argument_errors_before_any_device_call():
     assert lib.fmm_rank_candidates(64, 64, 64, 0, None, 0, 0.0, None, 0, ctypes.byref(cnt)) == 0 and cnt.value == 0
     # server options
     srv = vp()
-    for arena, batch, inflight in ((0, 8, 2), (1 << 20, 0, 2), (1 << 20, 65, 2), (1 << 20, 8, 0)):
-        opts = F._ServerOptions(arena, batch, inflight, 0)
+    zero3 = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    for batch, inflight, streams, large in ((0, 2, 1, 0.0), (65, 2, 1, 0.0), (8, 0, 1, 0.0), (8, 2, 5, 0.0),
+                                            (8, 2, -1, 0.0), (8, 2, 3, -1.0)):
+        opts = F._ServerOptions(1 << 20, batch, inflight, 0, 0, zero3, streams, large)
         assert lib.fmm_server_create(ctypes.byref(srv), ctypes.byref(opts), None) == 1
+    assert lib.fmm_server_arena_bytes(None) == 0
     assert lib.fmm_server_create(ctypes.byref(srv), None, None) == 1
     assert lib.fmm_server_submit(None, None, None) == 1
     n = ctypes.c_int(-1)
@@ -245,3 +248,28 @@ def test_argument_errors_before_any_device_call():
         with pytest.raises(F.FmmError) as e:
             autotune.record(*args)
         assert e.value.code == 1
+
+
+def test_leaf_form_choice_and_limits():
+    """Small one-level FP64 / FP32 plans form their leaf operands inside the
+    leaf GEMM by default; deeper, larger and BF16x3 plans do not, and asking
+    for it there is an error."""
+    with F.Plan("strassen_222_7", 512, 512, 512, 1, F.F64, host_only=True) as p:
+        assert p.info["leaf_form"] == 2
+    with F.Plan("strassen_222_7", 512, 512, 512, 1, F.F64, host_only=True, leaf_form=1) as p:
+        assert p.info["leaf_form"] == 0
+    with F.Plan("fmm_333_23", 600, 600, 600, 1, F.F32, host_only=True) as p:
+        assert p.info["leaf_form"] == 0  # columns of up to 7 non-zeros
+    with pytest.raises(F.FmmError):
+        F.Plan("fmm_333_23", 600, 600, 600, 1, F.F32, host_only=True, leaf_form=2)
+    with F.Plan("strassen_222_7", 8192, 8192, 8192, 1, F.F64, host_only=True) as p:
+        assert p.info["leaf_form"] == 0
+    with F.Plan("strassen_222_7", 8192, 8192, 8192, 1, F.F64, host_only=True, leaf_form=2) as p:
+        assert p.info["leaf_form"] == 2
+    for args in (("strassen_222_7", 512, 512, 512, 2, F.F64), ("strassen_222_7", 512, 512, 512, 1, F.F32_BF16X3)):
+        with F.Plan(*args, host_only=True) as p:
+            assert p.info["leaf_form"] == 0
+        with pytest.raises(F.FmmError):
+            F.Plan(*args, host_only=True, leaf_form=2)
+    with pytest.raises(F.FmmError):
+        F.Plan("strassen_222_7", 512, 512, 512, 1, F.F64, host_only=True, leaf_form=3)
