@@ -86,6 +86,21 @@ def strassen():
     return _from_formulas("strassen_222_7", 2, 2, 2, S, T, C)
 
 
+def winograd_222():
+    """The Strassen-Winograd variant of <2,2,2;7> (S. Winograd's 1971 form,
+    the one Section 3.3's common-subexpression discussion concerns): its
+    seven products written out as full sums of blocks.  Scheduled with shared
+    intermediates (S1 = A21 + A22, S2 = S1 - A11, S4 = A12 - S2; T1 = B12 - B11,
+    T2 = B22 - T1, T4 = T2 - B21; U2 = M1 + M6, U3 = U2 + M7, U4 = U2 + M5) it
+    needs 15 block additions against Strassen's 18; as a bilinear table its
+    columns are denser (24 additions without sharing)."""
+    S = ["A11", "A12", "A11 + A12 - A21 - A22", "A22", "A21 + A22", "A21 + A22 - A11", "A11 - A21"]
+    T = ["B11", "B21", "B22", "B11 - B12 - B21 + B22", "B12 - B11", "B11 - B12 + B22", "B22 - B12"]
+    C = {"C11": "M1 + M2", "C12": "M1 + M3 + M5 + M6",
+         "C21": "M1 - M4 + M6 + M7", "C22": "M1 + M5 + M6 + M7"}
+    return _from_formulas("winograd_222_7", 2, 2, 2, S, T, C)
+
+
 def laderman_333():
     """A rank-23 <3,3,3> decomposition (Table 2 lists rank 23 for <3,3,3>; the
     paper does not print coefficients).  This is Laderman's 1976 scheme
@@ -237,6 +252,8 @@ def get(name) -> Algorithm:
         return classical_222()
     if name == "fmm_333_23":
         return laderman_333()
+    if name == "winograd_222_7":
+        return winograd_222()
     if name == "fmm_223_11":
         # Strassen on two block columns of B and C, classical on the third
         return direct_sum_n([strassen(), classical(2, 2, 1)], name)
@@ -251,7 +268,7 @@ def get(name) -> Algorithm:
 
 
 def names() -> List[str]:
-    out = ["classical_222_8", "strassen_222_7", "fmm_333_23", "fmm_223_11", "fmm_225_18"]
+    out = ["classical_222_8", "strassen_222_7", "fmm_333_23", "fmm_223_11", "fmm_225_18", "winograd_222_7"]
     out += sorted(_PERMUTED)
     for fn in sorted(os.listdir(os.path.join(_HERE, "tables"))):
         if fn.endswith(".txt"):

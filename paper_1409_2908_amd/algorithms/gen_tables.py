@@ -45,6 +45,7 @@ RECIPES = [
     ("fmm_323_15", ("text",)),
     ("fmm_423_20", ("text",)),
     ("fmm_424_26", ("text",)),
+    ("winograd_222_7", ("text",)),
     ("fmm_332_15", ("perm", "fmm_323_15")),
     ("fmm_233_15", ("perm", "fmm_323_15")),
     ("fmm_324_20", ("perm", "fmm_423_20")),

@@ -519,3 +519,33 @@ def test_direct_sums_equal_their_parts(name):
     B = rng.integers(-5, 6, size=(a.K * 2, a.N * 4)).astype(np.float64)
     C = recursive.fmm(a, L, A, B)
     assert np.array_equal(C, A @ B)
+
+
+def test_winograd_variant_schedule_and_counts():
+    """The Strassen-Winograd table: the bilinear form has 24 block additions;
+    evaluated through the shared-intermediate schedule (15 additions, the
+    count the common-subexpression discussion of Section 3.3 starts from) on
+    integer blocks it gives the exact product, and so does the table."""
+    import numpy as np
+    a = algorithms.get("winograd_222_7")
+    assert (a.M, a.K, a.N, a.R) == (2, 2, 2, 7)
+    assert algorithms.additions(a) == 24
+    rng = np.random.default_rng(5)
+    A = rng.integers(-9, 10, (6, 6)).astype(object)
+    B = rng.integers(-9, 10, (6, 6)).astype(object)
+    A11, A12, A21, A22 = A[:3, :3], A[:3, 3:], A[3:, :3], A[3:, 3:]
+    B11, B12, B21, B22 = B[:3, :3], B[:3, 3:], B[3:, :3], B[3:, 3:]
+    adds = 0
+    def add(x, y, sign=1):
+        nonlocal adds
+        adds += 1
+        return x + sign * y
+    S1 = add(A21, A22); S2 = add(S1, A11, -1); S3 = add(A11, A21, -1); S4 = add(A12, S2, -1)
+    T1 = add(B12, B11, -1); T2 = add(B22, T1, -1); T3 = add(B22, B12, -1); T4 = add(T2, B21, -1)
+    M1, M2, M3, M4 = A11.dot(B11), A12.dot(B21), S4.dot(B22), A22.dot(T4)
+    M5, M6, M7 = S1.dot(T1), S2.dot(T2), S3.dot(T3)
+    U2 = add(M1, M6); U3 = add(U2, M7); U4 = add(U2, M5)
+    C = np.block([[add(M1, M2), add(U4, M3)], [add(U3, M4, -1), add(U3, M5)]])
+    assert adds == 15
+    assert (C == A.dot(B)).all()
+    assert (recursive.fmm(a, 1, A, B) == A.dot(B)).all()
