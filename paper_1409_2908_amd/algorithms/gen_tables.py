@@ -46,6 +46,9 @@ RECIPES = [
     ("fmm_423_20", ("text",)),
     ("fmm_424_26", ("text",)),
     ("winograd_222_7", ("text",)),
+    ("fmm_334_29", ("text",)),
+    ("fmm_343_29", ("perm", "fmm_334_29")),
+    ("fmm_433_29", ("perm", "fmm_334_29")),
     ("fmm_332_15", ("perm", "fmm_323_15")),
     ("fmm_233_15", ("perm", "fmm_323_15")),
     ("fmm_324_20", ("perm", "fmm_423_20")),
