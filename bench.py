@@ -210,14 +210,24 @@ def main():
 
     leaf_ms = stage_ms[F.STAGE_LEAF]
     leaf_tflops = info["leaf_flops"] / (leaf_ms * 1e-3) / 1e12
-    # the leaf launch's tile edge (the library's per-launch rule for FP64 / FP32)
+    # the leaf launch's tile edge (the library's per-launch rule for FP64 /
+    # FP32: 32 when there are at most half as many 64 x 64 tiles as compute
+    # units, 64 for launches that form their operands or have fewer 128 x 128
+    # tiles than units, else 128) and operand term slots (leaf_form)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     t128, rem = info["gemm_tiles"], info["gemm_tiles"] % (2 * cus)
-    tile = 64 if (t128 < cus or (t128 < 4 * cus and 0 < rem <= cus)) else 128
+    t64 = -(-info["leaf_m"] // 64) * -(-info["leaf_n"] // 64) * max(info["num_leaves"], 1)
+    nt = info["leaf_form"]
+    if 2 * t64 <= cus:
+        tile = 32
+    elif nt or t128 < cus or (t128 < 4 * cus and 0 < rem <= cus):
+        tile = 64
+    else:
+        tile = 128
     if dt == F.F64:
-        kernel, peak, tag = f"gemm_kernel<double, {tile}, {tile}>", FP64_PEAK_TFLOPS, f"gemm_f64_t{tile}"
+        kernel, peak, tag = f"gemm_kernel<double, {tile}, {tile}, {nt}>", FP64_PEAK_TFLOPS, f"gemm_f64_t{tile}"
     elif dt == F.F32:
-        kernel, peak, tag = f"gemm_kernel<float, {tile}, {tile}>", FP32_PEAK_TFLOPS, f"gemm_f32_t{tile}"
+        kernel, peak, tag = f"gemm_kernel<float, {tile}, {tile}, {nt}>", FP32_PEAK_TFLOPS, f"gemm_f32_t{tile}"
     else:
         # three bf16 products per FP32 product, priced at the bf16 matrix peak;
         # the library's per-launch rule: split leaf operands with whole

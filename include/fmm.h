@@ -123,10 +123,11 @@ typedef struct {
     int leaf_tile;     /* output tile edge of the leaf GEMM: 128 or 64 (FP64 / FP32 / BF16x3), or
                           256 (BF16x3 leaves with split operands; peel strips then take 128);
                           0 (default): chosen per launch -- BF16x3 leaves 256 when the launch has
-                          at least two 256 x 256 tiles per compute unit, otherwise 64 when the
-                          launch has fewer 128 x 128 tiles than the device has compute units,
-                          else 128.  Every tile edge gives the same bits.  Other values:
-                          FMM_EINVAL.  Batched launches always choose per launch. */
+                          at least two 256 x 256 tiles per compute unit; FP64 / FP32 launches 32
+                          when they have at most half as many 64 x 64 tiles as the device has
+                          compute units; otherwise 64 when the launch has fewer 128 x 128 tiles
+                          than compute units, else 128.  Every tile edge gives the same bits.
+                          Other values: FMM_EINVAL.  Batched launches always choose per launch. */
     double max_error;  /* automatic choice only (alg "auto" or levels -1): the largest
                           error_bound (fmm_plan_info_t) a chosen plan may have; 0: the dtype's
                           default (1e-12 FP64, 1e-4 FP32, 5e-4 BF16x3); < 0: no limit.

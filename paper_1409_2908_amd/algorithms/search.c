@@ -407,6 +407,10 @@ int main(int argc, char** argv) {
   long long since = 0, since_print = 0;
   int best = R;
   for (long long f = 0; f < max_flips && found < count; ++f) {
+    if ((f & ((1LL << 26) - 1)) == 0 && f) {
+      fprintf(stderr, "%lld flips: rank %d, lowest %d\n", f, R, best);
+      fflush(stderr);
+    }
     if (!flip()) continue;
     if (reduce()) {
       since = 0;

@@ -230,8 +230,8 @@ __global__ void __launch_bounds__(256) form2_kernel(FormArgs a) {
 // case) with two positions per thread, so each store instruction writes two
 // bf16 of a plane (4 bytes per lane) instead of one.  S operands (row-major
 // planes): positions (p, q) and (p, q + 1), a workgroup covering 512
-// consecutive columns of one row (1 KB of each plane; measured 5% faster than
-// four rows of 128 columns).  T operands (k-octets): positions (p, q) and
+// consecutive columns of one row (1 KB of each plane, as for T; four rows of
+// 128 columns measured the same).  T operands (k-octets): positions (p, q) and
 // (p + 1, q) of one octet, a wavefront covering 16 columns of one octet (256
 // contiguous bytes per plane, 1 KB per workgroup).  Same chains, in the same
 // order, as form_kernel.
