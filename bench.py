@@ -333,6 +333,8 @@ def run_serving(args):
                   num_streams=args.streams, large_flops=args.large_gflop * 1e9)
     cap_fast, _ = serving.run_stream(reqs, zeros, pools, **common)
     log(f"[serving] capacity, fast path: {cap_fast}")
+    cap_all, _ = serving.run_stream(reqs, zeros, pools, small_model=True, **common)
+    log(f"[serving] capacity, the model's plan for small requests too: {cap_all}")
     cap_cl, _ = serving.run_stream(reqs, zeros, pools, arena_bytes=arena, max_batch=1, max_inflight=1,
                                    alg="classical", levels=0)
     log(f"[serving] capacity, one-at-a-time classical: {cap_cl}")
@@ -366,7 +368,7 @@ def run_serving(args):
                    "streams": args.streams, "max_batch": args.max_batch, "max_inflight": args.max_inflight},
         "offered_req_per_s": round(rate, 3),
         "fast": fast, "fast_one_stream": fast1, "classical_one_at_a_time": cl,
-        "capacity_fast": cap_fast, "capacity_classical": cap_cl,
+        "capacity_fast": cap_fast, "capacity_classical": cap_cl, "capacity_model_for_small_requests": cap_all,
         "fast_graph": fast_graph, "capacity_fast_graph": cap_graph,
         "alone_vs_mix_checked": checked, "alone_vs_mix_checked_graph": checked_g,
         "oracle_sampled_rows": oracle_errors,

@@ -139,10 +139,10 @@ typedef struct {
                           the product is bit for bit the same (one-level FP64 / FP32 plans
                           whose U and V columns have at most 2 non-zeros, all +-1: Strassen
                           and its direct sums; else FMM_EINVAL); such launches run 64 x 64
-                          tiles whatever leaf_tile asks; 0 (default): 2 when allowed and the
-                          leaf launch has at most 256 tiles of 128 x 128 (it cannot fill the
-                          device, and the formation launch and its idle gap cost more than
-                          the leaves' extra loads), else 1 */
+                          (or 32 x 32) tiles whatever leaf_tile asks; 0 (default): 1.  It
+                          removes the formation launch and the idle gap before the leaves,
+                          but each leaf step issues one load per term, which made leaves
+                          with long K up to 2x slower, so it is asked for, not chosen */
 } fmm_plan_options_t;
 
 /* Plan C = A*B for an m x k by k x n product with `levels` recursive steps of
@@ -380,7 +380,12 @@ typedef struct {
     int num_streams;     /* 0 or 1: one stream; 2..4: large requests on stream 0, the rest
                             on the others (see above) */
     double large_flops;  /* 2mkn at or above which a request is large (0: the default
-                            FMM_SERVER_LARGE_FLOPS); used with num_streams >= 2 */
+                            FMM_SERVER_LARGE_FLOPS); the lanes' split with num_streams >= 2 */
+    int small_model;     /* 0 (default): a request below large_flops that names no plan
+                            (alg NULL / "auto", levels -1) runs the classical product, whose
+                            leaves join the batch's grouped launch; non-zero: the automatic
+                            choice for every request.  Large requests always take the
+                            automatic choice. */
 } fmm_server_options_t;
 
 typedef struct {

@@ -69,7 +69,7 @@ class _ServerOptions(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int),
                 ("max_inflight", ctypes.c_int), ("fuse_levels", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("max_error", ctypes.c_double * 3), ("num_streams", ctypes.c_int),
-                ("large_flops", ctypes.c_double)]
+                ("large_flops", ctypes.c_double), ("small_model", ctypes.c_int)]
 
 
 class _Request(ctypes.Structure):
@@ -365,14 +365,16 @@ class Server:
     tensors of every request alive until its completion has been returned."""
 
     def __init__(self, arena_bytes, max_batch=8, max_inflight=2, fuse_levels=0, stream=None, use_graph=False,
-                 max_error=(0.0, 0.0, 0.0), num_streams=1, large_flops=0.0):
+                 max_error=(0.0, 0.0, 0.0), num_streams=1, large_flops=0.0, small_model=False):
         """arena_bytes 0: the device's free memory less a reserve.  num_streams
         2-4: large requests (2mkn >= large_flops, 0 = the library default) run
-        one per batch on stream 0, the rest on the other streams."""
+        one per batch on stream 0, the rest on the other streams.  Requests
+        below large_flops without a named plan run the classical product
+        unless small_model."""
         self._s = ctypes.c_void_p()
         opts = _ServerOptions(int(arena_bytes), int(max_batch), int(max_inflight), int(fuse_levels),
                               1 if use_graph else 0, (ctypes.c_double * 3)(*[float(x) for x in max_error]),
-                              int(num_streams), float(large_flops))
+                              int(num_streams), float(large_flops), 1 if small_model else 0)
         sp = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
         _check(_lib.fmm_server_create(ctypes.byref(self._s), ctypes.byref(opts), sp))
         self._live = {}

@@ -231,11 +231,7 @@ struct PlanSummary {
   int leaf_form = 0;       // S and T formed inside the leaf GEMM (Plan::leaf_form)
 };
 
-// Plans whose leaf launch has at most this many 128 x 128 tiles form their
-// leaf operands inside the leaf GEMM by default (Plan::leaf_form): below it
-// the leaves cannot fill the device, so a separate formation launch, and the
-// idle gap before the leaves, costs more than the leaves' extra operand reads.
-constexpr int64_t kLeafFormMaxTiles = 256;
+
 
 // Plans of one level whose S and T passes together cover at most this many
 // output positions form both in one launch (Plan::pair_form).

@@ -387,8 +387,7 @@ std::string summarize_plan(PlanSummary& S, const char* alg, int64_t m, int64_t k
     S.pair_form = L == 1 && dtype != 2 && S.form_passes == 2 &&
                   (m0 / fm) * (k0 / fk) + (k0 / fk) * (n0 / fn) <= kPairFormMaxPositions;
     const int nt = leaf_form_terms(ids, L, dtype);
-    const int64_t leaf_tiles = ((ml + kTileM - 1) / kTileM) * ((nl + kTileN - 1) / kTileN) * nleaves;
-    S.leaf_form = (leaf_form == 2 || (leaf_form == 0 && leaf_tiles <= kLeafFormMaxTiles)) ? nt : 0;
+    S.leaf_form = leaf_form == 2 ? nt : 0;
     if (leaf_form == 2 && nt == 0) return "leaf_form 2 needs a one-level FP64 / FP32 plan";
   }
   for (GemmGroup& g : S.groups) {
@@ -663,10 +662,7 @@ std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n,
     if (leaf_form == 2 && nt == 0)
       return "leaf_form 2 needs a one-level FP64 / FP32 plan whose S and T columns have at most " +
              std::to_string(kMaxLeafTerms) + " non-zeros, each +-1";
-    const bool small = !P.gemm_groups.empty() &&
-                       P.gemm_groups[0].tiles_m * P.gemm_groups[0].tiles_n * P.gemm_groups[0].count <=
-                           kLeafFormMaxTiles;
-    P.leaf_form = (leaf_form == 2 || (leaf_form == 0 && small)) ? nt : 0;
+    P.leaf_form = leaf_form == 2 ? nt : 0;
   }
   if (P.leaf_form) {
     const AlgInfo& A = alg_info(P.lv_alg[0]);

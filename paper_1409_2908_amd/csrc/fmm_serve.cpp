@@ -536,7 +536,14 @@ fmm_status fmm_server_submit(fmm_server_t s, const fmm_request_t* req, int64_t* 
   q.r = r;
   q.submit_ms = s->now_ms();
   const bool auto_alg = !r.alg || !std::strcmp(r.alg, "auto");
-  if (auto_alg || r.levels < 0) {
+  const bool small = 2.0 * (double)r.m * (double)r.k * (double)r.n < s->opt.large_flops;
+  if (auto_alg && r.levels < 0 && small && !s->opt.small_model) {
+    // A small request joins a batch whose leaves share grouped launches; a
+    // fast plan would add its own formation and combination launches to the
+    // batch's stream, which costs more than the leaf flops it saves there.
+    q.alg = "classical";
+    q.levels = 0;
+  } else if (auto_alg || r.levels < 0) {
     // a measured choice for the exact shape if one was recorded, else the model
     fmm::Candidate pick;
     std::string why;

@@ -72,7 +72,8 @@ def percentile(x, q):
 
 
 def run_stream(requests, arrivals_ms, pools, arena_bytes, max_batch=8, max_inflight=2, alg=None,
-               levels=-1, keep=None, max_outstanding=64, use_graph=False, num_streams=1, large_flops=0.0):
+               levels=-1, keep=None, max_outstanding=64, use_graph=False, num_streams=1, large_flops=0.0,
+               small_model=False):
     """Replay the stream in real time through a server.  `alg`/`levels` apply
     to every request (None / -1: the library's per-shape choice).  At most
     `max_outstanding` requests are submitted and unfinished at once (their
@@ -89,7 +90,7 @@ def run_stream(requests, arrivals_ms, pools, arena_bytes, max_batch=8, max_infli
     batches = []
     algs = {}
     srv = Server(arena_bytes, max_batch=max_batch, max_inflight=max_inflight, use_graph=use_graph,
-                 num_streams=num_streams, large_flops=large_flops)
+                 num_streams=num_streams, large_flops=large_flops, small_model=small_model)
     arena_gb = srv.arena_bytes / 1e9
     lanes = {}
     torch.cuda.synchronize()

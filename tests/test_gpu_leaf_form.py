@@ -42,9 +42,7 @@ def _run(F, alg, A, B, dtype, leaf_form):
     m, k = A.shape
     n = B.shape[1]
     with F.Plan(alg, m, k, n, 1, dtype, leaf_form=leaf_form) as p:
-        assert p.info["leaf_form"] == (0 if leaf_form == 1 else p.info["leaf_form"])
-        if leaf_form == 2:
-            assert p.info["leaf_form"] == 2
+        assert p.info["leaf_form"] == (2 if leaf_form == 2 else 0)
         return to_host(p.multiply(to_dev(A), to_dev(B)))
 
 
@@ -96,7 +94,7 @@ def test_leaf_form_in_a_mixed_batch_graph_and_noalloc(F):
         np_dt = np.float64 if dt == F.F64 else np.float32
         A, B = fmm_inputs.operands(80 + i, m, k, n, "uniform", np_dt)
         dA, dB = to_dev(A), to_dev(B)
-        p = F.Plan(alg, m, k, n, 1, dt)
+        p = F.Plan(alg, m, k, n, 1, dt, leaf_form=2 if i in (0, 4) else 1)
         plans.append(p)
         ops.append((dA, dB))
         alone.append(to_host(p.multiply(dA, dB)))
@@ -115,7 +113,7 @@ def test_leaf_form_in_a_mixed_batch_graph_and_noalloc(F):
         p.close()
     alg, m, k, n, dt = shapes[0]
     dA, dB = ops[0]
-    with F.Plan(alg, m, k, n, 1, dt, use_graph=True) as p:
+    with F.Plan(alg, m, k, n, 1, dt, use_graph=True, leaf_form=2) as p:
         assert p.info["leaf_form"] == 2
         for _ in range(3):
             C = p.multiply(dA, dB)

@@ -61,8 +61,10 @@ def test_poisson_stream_alone_vs_mix_and_oracle():
     pools = serving.Pools(2048, seed=5)
     arr = serving.poisson_arrivals(23, n_req, 4000.0)
     say(f"case serving stream {n_req} requests")
+    # small_model: the model's choice for these small requests too, so that
+    # fast plans share batches
     stats, kept = serving.run_stream(reqs, arr, pools, arena_bytes=1 << 30, max_batch=8, max_inflight=2,
-                                     keep=set(range(n_req)), max_outstanding=32)
+                                     keep=set(range(n_req)), max_outstanding=32, small_model=True)
     say(f"  {stats}")
     assert stats["requests"] == n_req and stats["mean_batch"] > 1
     assert serving.check_alone(kept) == n_req
@@ -96,7 +98,8 @@ def test_graph_served_batches_equal_eager():
     arr = np.zeros(n_req)
     say(f"case graph-served stream {n_req} requests")
     stats, kept = serving.run_stream(reqs, arr, pools, arena_bytes=1 << 30, max_batch=8, max_inflight=2,
-                                     keep=set(range(n_req)), max_outstanding=32, use_graph=True)
+                                     keep=set(range(n_req)), max_outstanding=32, use_graph=True,
+                                     small_model=True)
     say(f"  {stats}")
     assert stats["requests"] == n_req and stats["mean_batch"] > 1
     assert serving.check_alone(kept) == n_req
@@ -130,9 +133,11 @@ def test_serving_workload_sizes_alone_vs_mix_and_oracle():
 
 def test_three_streams_classes_alone_vs_mix_and_oracle():
     """Three server streams: every request of 2mkn >= the large threshold runs
-    alone in its batch on stream 0, every other request on streams 1-2; each
-    result is bitwise the same plan run alone and within its gate against the
-    binary64 oracle on sampled rows (the lanes share no device memory)."""
+    alone in its batch on stream 0 with the model's plan, every other request
+    on streams 1-2 with the classical plan (the default for small requests);
+    each result is bitwise the same plan run alone and within its gate
+    against the binary64 oracle on sampled rows (the lanes share no device
+    memory)."""
     import torch
     import paper_1409_2908_amd as F
     from paper_1409_2908_amd import serving
@@ -156,7 +161,7 @@ def test_three_streams_classes_alone_vs_mix_and_oracle():
             n_large += 1
             assert c["lane"] == 0 and c["batch_size"] == 1, (idx, c)
         else:
-            assert c["lane"] in (1, 2), (idx, c)
+            assert c["lane"] in (1, 2) and c["alg"] == "classical", (idx, c)
     assert 0 < n_large < n_req
     assert set(stats["requests_per_stream"]) == {"0", "1", "2"}
     assert serving.check_alone(kept) == n_req

@@ -251,10 +251,13 @@ def test_argument_errors_before_any_device_call():
 
 
 def test_leaf_form_choice_and_limits():
-    """Small one-level FP64 / FP32 plans form their leaf operands inside the
-    leaf GEMM by default; deeper, larger and BF16x3 plans do not, and asking
-    for it there is an error."""
+    """One-level FP64 / FP32 plans of Strassen-type base cases form their leaf
+    operands inside the leaf GEMM when asked (never by default); deeper,
+    BF16x3 and wide-column plans cannot, and asking for it there is an
+    error."""
     with F.Plan("strassen_222_7", 512, 512, 512, 1, F.F64, host_only=True) as p:
+        assert p.info["leaf_form"] == 0
+    with F.Plan("strassen_222_7", 512, 512, 512, 1, F.F64, host_only=True, leaf_form=2) as p:
         assert p.info["leaf_form"] == 2
     with F.Plan("strassen_222_7", 512, 512, 512, 1, F.F64, host_only=True, leaf_form=1) as p:
         assert p.info["leaf_form"] == 0
