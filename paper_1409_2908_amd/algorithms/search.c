@@ -404,14 +404,20 @@ int main(int argc, char** argv) {
   const long long kGap = 1000;
   int found = 0, hit = 0;
   classical();
-  long long since = 0, since_print = 0;
+  long long since = 0, since_print = 0, stuck = 0;
   int best = R;
   for (long long f = 0; f < max_flips && found < count; ++f) {
     if ((f & ((1LL << 26) - 1)) == 0 && f) {
       fprintf(stderr, "%lld flips: rank %d, lowest %d\n", f, R, best);
       fflush(stderr);
     }
-    if (!flip()) continue;
+    if (!flip()) {
+      /* at the target rank with no two terms sharing a factor: no neighbour
+         to sample (Strassen's rank-7 schemes are such), so stop */
+      if (hit && ++stuck > 1000000) break;
+      continue;
+    }
+    stuck = 0;
     if (reduce()) {
       since = 0;
       if (R < best) best = R;
