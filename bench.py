@@ -224,7 +224,12 @@ def main():
         tile = 64
     else:
         tile = 128
-    if dt == F.F64:
+    if dt == F.F64 and tile == 128 and not nt and info["leaf_k"] % 2 == 0 and info["leaf_n"] % 2 == 0 \
+            and info["m0"] == m and info["k0"] == k and info["n0"] == n:
+        # operands staged by direct loads (the library's rule: 16-byte aligned
+        # rows, even leading dimensions, even K and N in every group)
+        kernel, peak, tag = "gemm_f64_dma_kernel", FP64_PEAK_TFLOPS, "gemm_f64dma_t128"
+    elif dt == F.F64:
         kernel, peak, tag = f"gemm_kernel<double, {tile}, {tile}, {nt}>", FP64_PEAK_TFLOPS, f"gemm_f64_t{tile}"
     elif dt == F.F32:
         kernel, peak, tag = f"gemm_kernel<float, {tile}, {tile}, {nt}>", FP32_PEAK_TFLOPS, f"gemm_f32_t{tile}"
@@ -412,7 +417,7 @@ def run_sweep(args):
             fl = 2.0 * n ** 3
             cms = timed(lambda: F.gemm(A, B, C))
             emit({"shape": [n, n, n], "alg": "classical", "levels": 0, "ms": cms, "tflops": fl / cms / 1e9})
-            for alg in ("strassen_222_7", "fmm_333_23", "fmm_323_15", "fmm_424_26"):
+            for alg in ("strassen_222_7", "winograd_222_7", "fmm_333_23", "fmm_323_15", "fmm_424_26", "fmm_334_29"):
                 for L in (1, 2, 3):
                     try:
                         p = F.Plan(alg, n, n, n, L, F.F64)

@@ -159,6 +159,25 @@ hipError_t run_form_pair(const fmm::Plan& P, const fmm::Bases& b, hipStream_t s)
   return fmm::launch_form_pair(fp[0]->alg, a[0], fp[0]->ngroups, a[1], fp[1]->ngroups, s);
 }
 
+// Whether every problem of plan P (or the single problem of a plain GEMM)
+// suits the FP64 direct-load leaf kernel: rows of A and B 16-byte aligned
+// with even leading dimensions (the kernel adds even row and column offsets),
+// even K and N in every group.
+bool ref_dma_ok(const fmm::Ref& r, const fmm::Bases& b, void* ws) {
+  const int64_t ld = r.buf == fmm::BUF_WS ? r.ld : b.ld[r.buf];
+  const void* base = r.buf == fmm::BUF_WS ? ws : b.ptr[r.buf];
+  return ld % 2 == 0 && (r.off + r.row * ld + r.col) % 2 == 0 && (uintptr_t)base % 16 == 0;
+}
+
+bool f64_dma_ok(const fmm::Plan& P, const fmm::Bases& b) {
+  if (P.dtype != 0 || P.leaf_form) return false;
+  for (const fmm::GemmGroup& g : P.gemm_groups)
+    if (g.n % 2 || g.k % 2) return false;
+  for (const fmm::GemmProb& pr : P.gemm_probs)
+    if (!ref_dma_ok(pr.a, b, P.ws) || !ref_dma_ok(pr.b, b, P.ws)) return false;
+  return true;
+}
+
 // Appends plan P's GEMM groups to a (possibly shared) grouped launch, with
 // P's operand bases in slot `slot`.
 void append_leaf(fmm::GemmArgs& a, const fmm::Plan& P, const fmm::Bases& b, int slot) {
@@ -181,6 +200,7 @@ hipError_t run_leaf(const fmm::Plan& P, const fmm::Bases& b, hipStream_t s) {
   append_leaf(a, P, b, 0);
   a.tile = P.leaf_tile;
   a.form_terms = P.leaf_form;
+  a.dma = f64_dma_ok(P, b) ? 1 : 0;
   return fmm::launch_gemm(a, P.dtype, num_cus(P.device), s);
 }
 
@@ -602,12 +622,15 @@ fmm_status fmm_multiply_batched(const fmm_plan_t* plans, const void* const* A, c
     fmm::GemmArgs a;
     std::memset(&a, 0, sizeof(a));
     int slots = 0;
+    bool dma = true;
     auto flush = [&]() -> hipError_t {
       hipError_t fe = hipSuccess;
       a.form_terms = form;
+      a.dma = dma ? 1 : 0;
       if (slots) fe = fmm::launch_gemm(a, dtype, num_cus(plans[live[0]]->P.device), s);
       std::memset(&a, 0, sizeof(a));
       slots = 0;
+      dma = true;
       return fe;
     };
     for (int i : live) {
@@ -616,6 +639,7 @@ fmm_status fmm_multiply_batched(const fmm_plan_t* plans, const void* const* A, c
       if (slots == fmm::kMaxGemmSlots || a.ngroups + (int)P.gemm_groups.size() > fmm::kMaxGemmGroups)
         if ((e = flush()) != hipSuccess) return hip_fail(e, "kernel launch");
       append_leaf(a, P, bases[i], slots++);
+      dma = dma && f64_dma_ok(P, bases[i]);
     }
     if ((e = flush()) != hipSuccess) return hip_fail(e, "kernel launch");
   }
@@ -785,6 +809,8 @@ fmm_status fmm_gemm(int dtype, int64_t m, int64_t k, int64_t n, const void* A, i
   g.probs = nullptr;
   g.slot = 0;
   a.total_tiles = g.tiles_m * g.tiles_n;
+  a.dma = dtype == 0 && n % 2 == 0 && k % 2 == 0 && ref_dma_ok(a.single.a, a.bases[0], nullptr) &&
+          ref_dma_ok(a.single.b, a.bases[0], nullptr);
   hipError_t e = fmm::launch_gemm(a, dtype, num_cus(dev), (hipStream_t)stream);
   return e == hipSuccess ? FMM_OK : hip_fail(e, "kernel launch");
 }

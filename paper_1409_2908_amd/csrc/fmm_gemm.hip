@@ -15,8 +15,11 @@
 // time through a double-buffered LDS stage: global loads for step k+1 are
 // issued before the MFMAs of step k and stored to the other LDS buffer before
 // its last quarter of MFMAs, one barrier per step.  Within a K step lane group g of a wavefront
-// supplies k = 4g + kk for MFMA kk (any bijection of k works when A and B use
-// the same one), so each lane reads its A fragment from one LDS row.
+// supplies k = 4g + kk (FP32) or k = 4kk + g (FP64) for MFMA kk (any bijection
+// of k works when A and B use the same one), so each lane reads its A
+// fragment from one LDS row.  Every FP64 kernel (all tile edges, and the
+// direct-load kernel in fmm_gemm_f64dma.hip) takes the FP64 bijection, so
+// they accumulate the same products in the same order.
 //
 // Operands are read and C is written with raw buffer instructions: a
 // per-step 128-bit resource in scalar registers plus one 32-bit byte offset
@@ -47,7 +50,9 @@ struct Mfma;
 template <>
 struct Mfma<double> {
   using acc_t = d4_t;
-  static constexpr int APAD = 1, BPAD = 4;
+  // B rows of BN + 16 doubles: the four k rows one fragment read touches
+  // (adjacent k, see the K loop) start 128 bytes apart in the LDS banks
+  static constexpr int APAD = 1, BPAD = 16;
   static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -281,9 +286,9 @@ gemm_kernel(GemmArgs args) {
         for (int kk = 0; kk < KPL; ++kk) {
           T af[TI], bf[TJ];
 #pragma unroll
-          for (int i = 0; i < TI; ++i) af[i] = As[cur][wm * WTM + i * 16 + li][lg * KPL + kk];
+          for (int i = 0; i < TI; ++i) af[i] = As[cur][wm * WTM + i * 16 + li][kk * 4 + lg];
 #pragma unroll
-          for (int j = 0; j < TJ; ++j) bf[j] = Bs[cur][lg * KPL + kk][wn * WTN + j * 16 + li];
+          for (int j = 0; j < TJ; ++j) bf[j] = Bs[cur][kk * 4 + lg][wn * WTN + j * 16 + li];
 #pragma unroll
           for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -393,6 +398,11 @@ static hipError_t launch_typed(const GemmArgs& a, int num_cus, hipStream_t s) {
 
 template <typename T>
 static hipError_t launch_forms(const GemmArgs& a, int num_cus, hipStream_t s) {
+  // FP64 launches on 128 x 128 tiles whose operands allow it stage them by
+  // direct loads (fmm_gemm_f64dma.hip); same products, same order
+  if (std::is_same_v<T, double> && a.form_terms == 0 && a.dma && !(a.tile == 0 && 2 * tiles64(a) <= num_cus) &&
+      pick_tile(a, num_cus) == 128)
+    return launch_gemm_f64_dma(a, num_cus, s);
   if (a.form_terms == 0) return launch_typed<T, 0>(a, num_cus, s);
   if (a.form_terms == kMaxLeafTerms) return launch_typed<T, kMaxLeafTerms>(a, num_cus, s);
   return hipErrorInvalidValue;

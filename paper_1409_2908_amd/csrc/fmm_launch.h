@@ -18,6 +18,9 @@ hipError_t launch_combine(int alg, const CombineArgs& a, int lv, int ngroups, hi
 // dtype (0: FP64 MFMA, 1: FP32 MFMA, 2: BF16x3 MFMA) select the kernel.
 hipError_t launch_gemm(const GemmArgs& a, int dtype, int num_cus, hipStream_t s);
 hipError_t launch_gemm_bf16x3(const GemmArgs& a, int num_cus, hipStream_t s);
+// FP64, 128 x 128 tiles, operands staged by direct global-to-LDS loads (a.dma
+// must be set: 16-byte aligned rows, even leading dimensions, even K and N).
+hipError_t launch_gemm_f64_dma(const GemmArgs& a, int num_cus, hipStream_t s);
 // Workgroups of a grouped leaf launch over `tiles` tiles, `resident` of
 // which fit on the device at once (a multiple of 8, at least 8).
 int64_t leaf_grid(int64_t resident, int64_t tiles);
