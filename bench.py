@@ -224,11 +224,16 @@ def main():
         tile = 64
     else:
         tile = 128
-    if dt == F.F64 and tile == 128 and not nt and info["leaf_k"] % 2 == 0 and info["leaf_n"] % 2 == 0 \
-            and info["m0"] == m and info["k0"] == k and info["n0"] == n:
+    e = 2 if dt == F.F64 else 4
+    dma = (dt in (F.F64, F.F32) and tile == 128 and not nt and info["leaf_k"] % e == 0 and
+           info["leaf_n"] % e == 0 and info["m0"] == m and info["k0"] == k and info["n0"] == n)
+    if dma:
         # operands staged by direct loads (the library's rule: 16-byte aligned
-        # rows, even leading dimensions, even K and N in every group)
-        kernel, peak, tag = "gemm_f64_dma_kernel", FP64_PEAK_TFLOPS, "gemm_f64dma_t128"
+        # rows, leading dimensions, K and N multiples of 16 bytes / element)
+        if dt == F.F64:
+            kernel, peak, tag = "gemm_f64_dma_kernel", FP64_PEAK_TFLOPS, "gemm_f64dma_t128"
+        else:
+            kernel, peak, tag = "gemm_f32_dma_kernel", FP32_PEAK_TFLOPS, "gemm_f32dma_t128"
     elif dt == F.F64:
         kernel, peak, tag = f"gemm_kernel<double, {tile}, {tile}, {nt}>", FP64_PEAK_TFLOPS, f"gemm_f64_t{tile}"
     elif dt == F.F32:

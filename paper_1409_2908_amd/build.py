@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfmm.so")
 SOURCES = ["fmm_api.cpp", "fmm_plan.cpp", "fmm_tune.cpp", "fmm_serve.cpp", "fmm_add.hip", "fmm_gemm.hip",
-           "fmm_gemm_bf16x3.hip", "fmm_gemm_f64dma.hip"]
+           "fmm_gemm_bf16x3.hip", "fmm_gemm_f64dma.hip", "fmm_gemm_f32dma.hip"]
 # plus one generated source per base case (csrc/gen/fmm_add_NN.hip), listed by gen_tables.generate()
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -160,21 +160,23 @@ hipError_t run_form_pair(const fmm::Plan& P, const fmm::Bases& b, hipStream_t s)
 }
 
 // Whether every problem of plan P (or the single problem of a plain GEMM)
-// suits the FP64 direct-load leaf kernel: rows of A and B 16-byte aligned
-// with even leading dimensions (the kernel adds even row and column offsets),
-// even K and N in every group.
-bool ref_dma_ok(const fmm::Ref& r, const fmm::Bases& b, void* ws) {
+// suits the direct-load leaf kernels (FP64 and FP32 MFMA paths): rows of A
+// and B 16-byte aligned with leading dimensions a multiple of e = 16 bytes /
+// element size (the kernels add row offsets and column offsets that keep
+// that alignment), and K and N multiples of e in every group.
+bool ref_dma_ok(const fmm::Ref& r, const fmm::Bases& b, void* ws, int e) {
   const int64_t ld = r.buf == fmm::BUF_WS ? r.ld : b.ld[r.buf];
   const void* base = r.buf == fmm::BUF_WS ? ws : b.ptr[r.buf];
-  return ld % 2 == 0 && (r.off + r.row * ld + r.col) % 2 == 0 && (uintptr_t)base % 16 == 0;
+  return ld % e == 0 && (r.off + r.row * ld + r.col) % e == 0 && (uintptr_t)base % 16 == 0;
 }
 
-bool f64_dma_ok(const fmm::Plan& P, const fmm::Bases& b) {
-  if (P.dtype != 0 || P.leaf_form) return false;
+bool leaf_dma_ok(const fmm::Plan& P, const fmm::Bases& b) {
+  if (P.dtype == 2 || P.leaf_form) return false;
+  const int e = P.dtype == 0 ? 2 : 4;
   for (const fmm::GemmGroup& g : P.gemm_groups)
-    if (g.n % 2 || g.k % 2) return false;
+    if (g.n % e || g.k % e) return false;
   for (const fmm::GemmProb& pr : P.gemm_probs)
-    if (!ref_dma_ok(pr.a, b, P.ws) || !ref_dma_ok(pr.b, b, P.ws)) return false;
+    if (!ref_dma_ok(pr.a, b, P.ws, e) || !ref_dma_ok(pr.b, b, P.ws, e)) return false;
   return true;
 }
 
@@ -200,7 +202,7 @@ hipError_t run_leaf(const fmm::Plan& P, const fmm::Bases& b, hipStream_t s) {
   append_leaf(a, P, b, 0);
   a.tile = P.leaf_tile;
   a.form_terms = P.leaf_form;
-  a.dma = f64_dma_ok(P, b) ? 1 : 0;
+  a.dma = leaf_dma_ok(P, b) ? 1 : 0;
   return fmm::launch_gemm(a, P.dtype, num_cus(P.device), s);
 }
 
@@ -639,7 +641,7 @@ fmm_status fmm_multiply_batched(const fmm_plan_t* plans, const void* const* A, c
       if (slots == fmm::kMaxGemmSlots || a.ngroups + (int)P.gemm_groups.size() > fmm::kMaxGemmGroups)
         if ((e = flush()) != hipSuccess) return hip_fail(e, "kernel launch");
       append_leaf(a, P, bases[i], slots++);
-      dma = dma && f64_dma_ok(P, bases[i]);
+      dma = dma && leaf_dma_ok(P, bases[i]);
     }
     if ((e = flush()) != hipSuccess) return hip_fail(e, "kernel launch");
   }
@@ -809,8 +811,11 @@ fmm_status fmm_gemm(int dtype, int64_t m, int64_t k, int64_t n, const void* A, i
   g.probs = nullptr;
   g.slot = 0;
   a.total_tiles = g.tiles_m * g.tiles_n;
-  a.dma = dtype == 0 && n % 2 == 0 && k % 2 == 0 && ref_dma_ok(a.single.a, a.bases[0], nullptr) &&
-          ref_dma_ok(a.single.b, a.bases[0], nullptr);
+  {
+    const int e = dtype == 0 ? 2 : 4;
+    a.dma = dtype != 2 && n % e == 0 && k % e == 0 && ref_dma_ok(a.single.a, a.bases[0], nullptr, e) &&
+            ref_dma_ok(a.single.b, a.bases[0], nullptr, e);
+  }
   hipError_t e = fmm::launch_gemm(a, dtype, num_cus(dev), (hipStream_t)stream);
   return e == hipSuccess ? FMM_OK : hip_fail(e, "kernel launch");
 }

@@ -398,11 +398,10 @@ static hipError_t launch_typed(const GemmArgs& a, int num_cus, hipStream_t s) {
 
 template <typename T>
 static hipError_t launch_forms(const GemmArgs& a, int num_cus, hipStream_t s) {
-  // FP64 launches on 128 x 128 tiles whose operands allow it stage them by
-  // direct loads (fmm_gemm_f64dma.hip); same products, same order
-  if (std::is_same_v<T, double> && a.form_terms == 0 && a.dma && !(a.tile == 0 && 2 * tiles64(a) <= num_cus) &&
-      pick_tile(a, num_cus) == 128)
-    return launch_gemm_f64_dma(a, num_cus, s);
+  // launches on 128 x 128 tiles whose operands allow it stage them by direct
+  // loads (fmm_gemm_f64dma.hip, fmm_gemm_f32dma.hip); same products, same order
+  if (a.form_terms == 0 && a.dma && !(a.tile == 0 && 2 * tiles64(a) <= num_cus) && pick_tile(a, num_cus) == 128)
+    return std::is_same_v<T, double> ? launch_gemm_f64_dma(a, num_cus, s) : launch_gemm_f32_dma(a, num_cus, s);
   if (a.form_terms == 0) return launch_typed<T, 0>(a, num_cus, s);
   if (a.form_terms == kMaxLeafTerms) return launch_typed<T, kMaxLeafTerms>(a, num_cus, s);
   return hipErrorInvalidValue;

@@ -21,7 +21,7 @@
 // half g % 2) and its B read (k row 4 kk + g, column li) then touch 64
 // distinct 4-byte banks across each half-wavefront.
 //
-// Requirements (checked on the host, f64_dma_ok): every problem's A and B
+// Requirements (checked on the host, leaf_dma_ok): every problem's A and B
 // rows start 16-byte aligned with even leading dimensions, and every group
 // has even K and N, so a k pair or column pair never straddles the end of a
 // row.  Rows past M, column pairs past N and k pairs past K read through an

@@ -127,7 +127,7 @@ struct GemmArgs {
   int elt;
   int tile;  // output tile edge of the FP64 / FP32 kernel: 64, 128, or 0 (chosen at launch)
   int form_terms;  // 0: plain operands; kMaxLeafTerms: every problem forms A and B from LeafTerms
-  int dma;         // FP64: every problem's operands allow the direct-load kernel (f64_dma_ok)
+  int dma;         // FP64 / FP32: every problem's operands allow the direct-load kernels (leaf_dma_ok)
   int pad_;
   int64_t total_tiles;
   GemmGroup groups[kMaxGemmGroups];

@@ -21,6 +21,9 @@ hipError_t launch_gemm_bf16x3(const GemmArgs& a, int num_cus, hipStream_t s);
 // FP64, 128 x 128 tiles, operands staged by direct global-to-LDS loads (a.dma
 // must be set: 16-byte aligned rows, even leading dimensions, even K and N).
 hipError_t launch_gemm_f64_dma(const GemmArgs& a, int num_cus, hipStream_t s);
+// FP32 (FP32 MFMA path) likewise: 16-byte aligned rows, leading dimensions,
+// K and N multiples of 4.
+hipError_t launch_gemm_f32_dma(const GemmArgs& a, int num_cus, hipStream_t s);
 // Workgroups of a grouped leaf launch over `tiles` tiles, `resident` of
 // which fit on the device at once (a multiple of 8, at least 8).
 int64_t leaf_grid(int64_t resident, int64_t tiles);
