@@ -47,7 +47,7 @@ __device__ __forceinline__ int brow(int k) { return (k >> 1) * SBC + (k & 1) * S
 __device__ __forceinline__ void f32_tile_dma(F32DmaSmem& sm, const float* A, const float* B, float* C, int lda,
                                              int ldb, int ldc, int mrem, int nrem, int K, float alpha) {
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave >> 1, wn = wave & 1;
   const int li = lane & 15, lg = lane >> 4;
   typedef __attribute__((address_space(3))) void* lds_ptr;
@@ -68,20 +68,38 @@ __device__ __forceinline__ void f32_tile_dma(F32DmaSmem& sm, const float* A, con
   const int b_row = lane >> 5;
   const int b_off = (b_row * ldb + 4 * (lane & 31)) * 4;
   const bool b_ok = 4 * (lane & 31) < nrem;
+  // a step wholly inside K needs only the row / column checks, folded into
+  // the offsets once; the tail step and the steps past K check every k
+  int a_offv[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) a_offv[q] = a_ok[q] ? a_off[q] : kInvalidOff;
+  const int b_offv = b_ok ? b_off : kInvalidOff;
   auto dma = [&](int buf, int k0) {
     const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + k0);
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr)&sm.a[buf][(32 * wave + 16 * q) * 4], 16,
-                                               (a_ok[q] && k0 + 4 * a_p[q] < K) ? a_off[q] : kInvalidOff, 0, 0,
-                                               0);
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(B + (int64_t)k0 * ldb);
+    if (k0 + SBK <= K) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int c = 2 * wave + q;
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr)&sm.b[buf][c * SBC], 16,
-                                               (b_ok && k0 + 2 * c + b_row < K) ? b_off : kInvalidOff,
-                                               uniform_int(2 * c * ldb * 4), 0, 0);
+      for (int q = 0; q < 2; ++q)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr)&sm.a[buf][(32 * wave + 16 * q) * 4], 16, a_offv[q], 0,
+                                                 0, 0);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int c = 2 * wave + q;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr)&sm.b[buf][c * SBC], 16, b_offv, 2 * c * ldb * 4, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr)&sm.a[buf][(32 * wave + 16 * q) * 4], 16,
+                                                 (a_ok[q] && k0 + 4 * a_p[q] < K) ? a_off[q] : kInvalidOff, 0, 0,
+                                                 0);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int c = 2 * wave + q;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr)&sm.b[buf][c * SBC], 16,
+                                                 (b_ok && k0 + 2 * c + b_row < K) ? b_off : kInvalidOff,
+                                                 2 * c * ldb * 4, 0, 0);
+      }
     }
   };
 
@@ -94,9 +112,10 @@ __device__ __forceinline__ void f32_tile_dma(F32DmaSmem& sm, const float* A, con
   constexpr int kWaitVm0 = 0x0F70;  // vmcnt(0) only
   const int nk = (K + SBK - 1) / SBK;
   // A fragments: the four k values of the step in one read per row block; B
-  // fragments per sub-step.  The next step's loads go out at the top of the
-  // step into the buffer every wavefront finished reading before the previous
-  // barrier; the last step loads a step past K (zeros nothing reads).
+  // fragments per sub-step.  The loads of the step after next go out right
+  // after the barrier into the buffer every wavefront has just finished
+  // reading, so they have a whole step of MFMAs to land in; the last two
+  // steps load steps past K (zeros nothing reads).
   f4_t af[4];
   float bf[4][4];
   auto rd = [&](int buf) {
@@ -110,9 +129,9 @@ __device__ __forceinline__ void f32_tile_dma(F32DmaSmem& sm, const float* A, con
   dma(0, 0);
   __builtin_amdgcn_s_waitcnt(kWaitVm0);
   __syncthreads();
+  dma(1, SBK);
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    dma(cur ^ 1, (kt + 1) * SBK);
     rd(cur);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk)
@@ -123,7 +142,12 @@ __device__ __forceinline__ void f32_tile_dma(F32DmaSmem& sm, const float* A, con
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][kk], bf[kk][j], acc[i][j], 0, 0, 0);
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
+    dma(cur, (kt + 2) * SBK);
   }
+  // the loads past K have landed and every read is done before the next
+  // tile's first loads reuse the buffers
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);
+  __syncthreads();
 
   const __amdgpu_buffer_rsrc_t sc = make_rsrc(C);
 #pragma unroll
@@ -160,8 +184,6 @@ gemm_f32_dma_kernel(GemmArgs args) {
     f32_tile_dma(sm, A, B, C, uniform_int((int)lda), uniform_int((int)ldb), uniform_int((int)ldc),
                  uniform_int(mr < SBM ? (int)mr : SBM), uniform_int(nr < SBM ? (int)nr : SBM),
                  uniform_int((int)job.k), (float)uniform_double(pr.alpha));
-    // the next tile's first loads rewrite buffer 0
-    __syncthreads();
   }
 }
 

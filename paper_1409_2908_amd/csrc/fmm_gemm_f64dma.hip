@@ -54,7 +54,7 @@ __device__ __forceinline__ void f64_tile_dma(F64DmaSmem& sm, const double* A, co
                                              int lda, int ldb, int ldc, int mrem, int nrem, int K,
                                              double alpha) {
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave >> 1, wn = wave & 1;
   const int li = lane & 15, lg = lane >> 4;
   typedef __attribute__((address_space(3))) void* lds_ptr;
@@ -73,20 +73,38 @@ __device__ __forceinline__ void f64_tile_dma(F64DmaSmem& sm, const double* A, co
   // B: wavefront w fills k rows 4 w .. 4 w + 3; lane i covers columns 2i, 2i + 1
   const int b_off = 16 * lane;
   const bool b_ok = 2 * lane < nrem;
+  // a step wholly inside K needs only the row / column checks, folded into
+  // the offsets once; the tail step (and the steps past K that the pipeline
+  // loads) check every k pair and k row
+  int a_offv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) a_offv[q] = a_ok[q] ? a_off[q] : kInvalidOff;
+  const int b_offv = b_ok ? b_off : kInvalidOff;
   auto dma = [&](int buf, int k0) {
     const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + k0);
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr)&sm.a[buf][(32 * wave + 8 * q) * QBK], 16,
-                                               (a_ok[q] && k0 + 2 * a_p[q] < K) ? a_off[q] : kInvalidOff, 0, 0,
-                                               0);
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(B + (int64_t)k0 * ldb);
+    if (k0 + QBK <= K) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kk = 4 * wave + q;
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr)&sm.b[buf][kk * QBS], 16,
-                                               (b_ok && k0 + kk < K) ? b_off : kInvalidOff,
-                                               uniform_int(kk * ldb * 8), 0, 0);
+      for (int q = 0; q < 4; ++q)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr)&sm.a[buf][(32 * wave + 8 * q) * QBK], 16, a_offv[q], 0,
+                                                 0, 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = 4 * wave + q;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr)&sm.b[buf][kk * QBS], 16, b_offv, kk * ldb * 8, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr)&sm.a[buf][(32 * wave + 8 * q) * QBK], 16,
+                                                 (a_ok[q] && k0 + 2 * a_p[q] < K) ? a_off[q] : kInvalidOff, 0, 0,
+                                                 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = 4 * wave + q;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr)&sm.b[buf][kk * QBS], 16,
+                                                 (b_ok && k0 + kk < K) ? b_off : kInvalidOff, kk * ldb * 8, 0, 0);
+      }
     }
   };
 
@@ -102,11 +120,13 @@ __device__ __forceinline__ void f64_tile_dma(F64DmaSmem& sm, const double* A, co
   const int nk = (K + QBK - 1) / QBK;
   // Fragments are read one sub-step ahead of their MFMAs (two register
   // sets), and the barrier sits between the third and the fourth sub-step:
-  // every read of the current buffer is issued before it and the next step's
-  // direct loads (issued at the top of the step, three sub-steps earlier)
-  // have landed after it, so the next step's first fragments are read while
-  // the fourth sub-step's MFMAs run.  The last step loads a step past K,
-  // which writes zeros nothing reads, so the loop body has no branch.
+  // every read of the current buffer is issued before it, and the direct
+  // loads of the step after next go out right after it into the buffer just
+  // released, so they have a whole step of MFMAs to land in.  The next
+  // step's first fragments are read while the fourth sub-step's MFMAs run.
+  // Scheduling fences keep the compiler from sinking a fragment read down to
+  // its MFMAs (which would expose the LDS latency) or the loads below them.
+  // The last two steps load steps past K, which write zeros nothing reads.
   double af[2][4], bf[2][4];
   auto rd = [&](int buf, int kk) {
     const int p = 2 * kk + (lg >> 1), h = lg & 1, s = kk & 1;
@@ -122,26 +142,38 @@ __device__ __forceinline__ void f64_tile_dma(F64DmaSmem& sm, const double* A, co
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s][i], bf[s][j], acc[i][j], 0, 0, 0);
   };
+  auto fence = [] { __builtin_amdgcn_sched_barrier(0); };
   dma(0, 0);
   __builtin_amdgcn_s_waitcnt(kWaitVm0);
   __syncthreads();
+  dma(1, QBK);
   rd(0, 0);
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    dma(cur ^ 1, (kt + 1) * QBK);
     rd(cur, 1);
+    fence();
     mma(0);
+    fence();
     rd(cur, 2);
+    fence();
     mma(1);
+    fence();
     rd(cur, 3);
+    fence();
     mma(2);
+    fence();
+    // step kt + 1's loads have landed and every wavefront is done with buffer cur
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
     rd(cur ^ 1, 0);
+    fence();
+    dma(cur, (kt + 2) * QBK);
     mma(3);
+    fence();
   }
-  // the last step read a step past K into registers only; its buffer is
-  // rewritten by the next tile's first loads after this barrier
+  // the loads past K have landed before the next tile's first loads reuse
+  // the buffers
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);
   __syncthreads();
 
   const __amdgpu_buffer_rsrc_t sc = make_rsrc(C);
