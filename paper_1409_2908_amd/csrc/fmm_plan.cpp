@@ -22,6 +22,17 @@ int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 size_t elt_size(int elt) { return elt == ELT_F64 ? 8 : 4; }
 
+// Leading dimension of a workspace matrix of width w (elements of es bytes):
+// a multiple of 16 elements; FP64 rows of 2 KB or more get 16 more, so that
+// the rows of one leaf tile are not a power-of-two stride apart (such rows
+// crowd into a few L2 sets and memory channels).  Measured at 16384^3: the
+// FP64 leaf launch gains 2%; FP32 leaves gain less than the FP32
+// combination pass loses reading padded products, so FP32 rows stay unpadded.
+int64_t ws_ld(int64_t w, size_t es) {
+  const int64_t ld = round_up(w, 16);
+  return es == 8 && ld * 8 >= 2048 ? ld + 16 : ld;
+}
+
 struct Arena {
   size_t used = 0;
   // Returns the byte offset of a fresh 256-byte aligned region.
@@ -181,8 +192,8 @@ std::vector<Ref> plan_side(Plan& P, int side, Arena& ws, std::vector<FormPass>& 
     fp.depth_in = depth;
     fp.h = rows0 / rdiv[d2];
     fp.w = cols0 / cdiv[d2];
-    fp.out_ld = round_up(fp.w, 16);
     fp.out_elt = split ? ELT_BF16X2 : final_pass ? P.elt : ELT_F64;
+    fp.out_ld = ws_ld(fp.w, elt_size(fp.out_elt));
     fp.ngroups = (int)nodes.size();
     fp.nout = (int)ipow(R, lv);
     size_t region = (size_t)fp.h * fp.out_ld * elt_size(fp.out_elt);
@@ -304,7 +315,7 @@ void summarize_side(const std::vector<int>& ids, int side, int fuse, int dtype, 
       ws.alloc_many(mat, (size_t)plane * 4);
       *bytes += (double)mat * h * w * 4;
     } else {
-      ws.alloc_many(mat, (size_t)h * round_up(w, 16) * elt_size(out_elt));
+      ws.alloc_many(mat, (size_t)h * ws_ld(w, elt_size(out_elt)) * elt_size(out_elt));
       *bytes += (double)mat * h * w * elt_size(out_elt);
     }
     const int64_t in_views = g_in * nv, f64_kept = f64_views ? g_f64 * nv : 0;
@@ -350,7 +361,7 @@ std::string summarize_plan(PlanSummary& S, const char* alg, int64_t m, int64_t k
     summarize_side(ids, 0, S.fuse, dtype, elt, m0, k0, ws, &S.add_bytes, &S.form_passes);
     summarize_side(ids, 1, S.fuse, dtype, elt, k0, n0, ws, &S.add_bytes, &S.form_passes);
     const int64_t nleaves = prr[L];
-    const int64_t m_ld = round_up(nl, 16);
+    const int64_t m_ld = ws_ld(nl, es);
     const int64_t m_stride = round_up(ml * m_ld * (int64_t)es, 256) / (int64_t)es;
     ws.alloc_many(1, (size_t)m_stride * es * nleaves);
     S.groups.push_back(GemmGroup{ml, nl, kl, nleaves, 0, 0, 0, 0});
@@ -516,7 +527,7 @@ std::string make_plan(Plan& P, const char* alg, int64_t m, int64_t k, int64_t n,
     std::vector<Ref> T = plan_side(P, 1, ws, P.t_passes, &P.t_mat, &add_bytes);
     const int64_t nleaves = prr[L];
     // Leaf products M_rho, contiguous with a uniform stride.
-    const int64_t m_ld = round_up(P.nl, 16);
+    const int64_t m_ld = ws_ld(P.nl, es);
     const int64_t m_stride = round_up(P.ml * m_ld * (int64_t)es, 256) / (int64_t)es;
     const size_t m_base = ws.alloc((size_t)m_stride * es * nleaves);
     GemmGroup g0{P.ml, P.nl, P.kl, nleaves, 0, 0, 0, 0};
