@@ -188,7 +188,7 @@ def main():
     # error on sampled rows + CPU baseline (the oracle on those rows)
     plan.multiply(dA, dB, dC)
     torch.cuda.synchronize()
-    err = None
+    err = err_max_row = err_unscaled = None
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import classical as oracle_classical
@@ -201,6 +201,14 @@ def main():
         ref = oracle_classical.gemm_rows(A, B, rows)
         tc1 = time.perf_counter()
         err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        # the worst single row, and (row-scaled inputs) the rows of C whose
+        # row of A was not scaled, which the scaled rows' magnitude would
+        # otherwise hide in the Frobenius norm
+        row_err = np.linalg.norm(got - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-300)
+        err_max_row = float(row_err.max())
+        if dt != F.F64:
+            unscaled = ~np.isin(rows, fmm_inputs.scaled_rows(0, m, "A"))
+            err_unscaled = float(np.linalg.norm(got[unscaled] - ref[unscaled]) / np.linalg.norm(ref[unscaled]))
         cpu_flops = 2.0 * len(rows) * k * n
         cpu = {"value": cpu_flops / (tc1 - tc0) / 1e12, "unit": "TFLOP/s",
                "cores": oracle_classical.num_threads(), "kind": "oracle",
@@ -277,6 +285,8 @@ def main():
         "speedup_vs_classical": round(eff_tflops / classical_tflops, 4),
         "speedup_vs_vendor": round(eff_tflops / vendor_tflops, 4),
         "error_relF_sampled_rows": err,
+        "error_max_row_relF": err_max_row,
+        "error_relF_unscaled_rows": err_unscaled,
         "stage_ms": {"form_s": stage_ms[0], "form_t": stage_ms[1], "leaf_gemm": stage_ms[2],
                      "combine": stage_ms[3]},
         "roofline": {"bound": "mfma", "kernel": kernel,
