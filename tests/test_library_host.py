@@ -179,6 +179,21 @@ def test_workspace_and_addition_bytes_model():
     assert i["add_bytes"] == reads + writes
 
 
+def test_workspace_row_padding():
+    """FP64 workspace operands whose rows span 2 KB or more are stored 16
+    elements wider (no power-of-two row stride across a leaf tile); narrower
+    FP64 rows and FP32 rows keep the 16-element rounding only; views into A
+    and B keep the caller's leading dimension."""
+    with F.Plan("strassen_222_7", 512, 512, 512, 1, host_only=True) as p:
+        ld_ws = {p.operand(0, r)[4] for r in range(7) if p.operand(0, r)[0] == F.LOC_WORKSPACE}
+        ld_view = {p.operand(0, r)[4] for r in range(7) if p.operand(0, r)[0] == F.LOC_A}
+        assert ld_ws == {256 + 16} and ld_view == {0}
+    with F.Plan("strassen_222_7", 256, 256, 256, 1, host_only=True) as p:
+        assert {p.operand(1, r)[4] for r in range(7) if p.operand(1, r)[0] == F.LOC_WORKSPACE} == {128}
+    with F.Plan("strassen_222_7", 512, 512, 512, 1, F.F32, host_only=True) as p:
+        assert {p.operand(0, r)[4] for r in range(7) if p.operand(0, r)[0] == F.LOC_WORKSPACE} == {256}
+
+
 def test_zero_sizes_are_valid():
     for (m, k, n) in [(0, 5, 5), (5, 0, 5), (5, 5, 0), (0, 0, 0)]:
         p = F.Plan("strassen_222_7", m, k, n, 2, host_only=True)
