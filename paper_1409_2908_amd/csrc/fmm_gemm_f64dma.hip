@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <type_traits>
 
 #include "fmm_device.h"
 #include "fmm_gemm_common.h"
@@ -74,16 +75,16 @@ __device__ __forceinline__ void f64_tile_dma(F64DmaSmem& sm, const double* A, co
   const int b_off = 16 * lane;
   const bool b_ok = 2 * lane < nrem;
   // a step wholly inside K needs only the row / column checks, folded into
-  // the offsets once; the tail step (and the steps past K that the pipeline
-  // loads) check every k pair and k row
+  // the offsets once (`checked` false); the tail step and the steps past K
+  // that the pipeline loads check every k pair and k row
   int a_offv[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) a_offv[q] = a_ok[q] ? a_off[q] : kInvalidOff;
   const int b_offv = b_ok ? b_off : kInvalidOff;
-  auto dma = [&](int buf, int k0) {
+  auto dma = [&](int buf, int k0, auto checked) {
     const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + k0);
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(B + (int64_t)k0 * ldb);
-    if (k0 + QBK <= K) {
+    if constexpr (!decltype(checked)::value) {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
         __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr)&sm.a[buf][(32 * wave + 8 * q) * QBK], 16, a_offv[q], 0,
@@ -143,12 +144,14 @@ __device__ __forceinline__ void f64_tile_dma(F64DmaSmem& sm, const double* A, co
       for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s][i], bf[s][j], acc[i][j], 0, 0, 0);
   };
   auto fence = [] { __builtin_amdgcn_sched_barrier(0); };
-  dma(0, 0);
+  constexpr std::true_type kChecked{};
+  constexpr std::false_type kPlain{};
+  dma(0, 0, kChecked);
   __builtin_amdgcn_s_waitcnt(kWaitVm0);
   __syncthreads();
-  dma(1, QBK);
+  dma(1, QBK, kChecked);
   rd(0, 0);
-  for (int kt = 0; kt < nk; ++kt) {
+  auto step = [&](int kt, auto checked) {
     const int cur = kt & 1;
     rd(cur, 1);
     fence();
@@ -162,15 +165,29 @@ __device__ __forceinline__ void f64_tile_dma(F64DmaSmem& sm, const double* A, co
     fence();
     mma(2);
     fence();
-    // step kt + 1's loads have landed and every wavefront is done with buffer cur
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
     rd(cur ^ 1, 0);
     fence();
-    dma(cur, (kt + 2) * QBK);
+    dma(cur, (kt + 2) * QBK, checked);
     mma(3);
+    if constexpr (!decltype(checked)::value) {
+      // one direct load between every two MFMAs of the last sub-step, so
+      // the loads leave in a steady stream instead of one burst per step
+#pragma unroll
+      for (int g = 0; g < 8; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // a VMEM read
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // two MFMAs
+      }
+    }
     fence();
-  }
+  };
+  // the steps whose loads (two steps ahead) lie wholly inside K run a loop
+  // body without branches, which the interleaving needs
+  const int nplain = K / QBK - 2 > 0 ? K / QBK - 2 : 0;
+  int kt = 0;
+  for (; kt < nplain; ++kt) step(kt, kPlain);
+  for (; kt < nk; ++kt) step(kt, kChecked);
   // the loads past K have landed before the next tile's first loads reuse
   // the buffers
   __builtin_amdgcn_s_waitcnt(kWaitVm0);
