@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <type_traits>
 
 #include "fmm_device.h"
 #include "fmm_gemm_common.h"
@@ -69,15 +70,16 @@ __device__ __forceinline__ void f32_tile_dma(F32DmaSmem& sm, const float* A, con
   const int b_off = (b_row * ldb + 4 * (lane & 31)) * 4;
   const bool b_ok = 4 * (lane & 31) < nrem;
   // a step wholly inside K needs only the row / column checks, folded into
-  // the offsets once; the tail step and the steps past K check every k
+  // the offsets once (`checked` false); the tail step and the step past K
+  // check every k
   int a_offv[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) a_offv[q] = a_ok[q] ? a_off[q] : kInvalidOff;
   const int b_offv = b_ok ? b_off : kInvalidOff;
-  auto dma = [&](int buf, int k0) {
+  auto dma = [&](int buf, int k0, auto checked) {
     const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + k0);
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(B + (int64_t)k0 * ldb);
-    if (k0 + SBK <= K) {
+    if constexpr (!decltype(checked)::value) {
 #pragma unroll
       for (int q = 0; q < 2; ++q)
         __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr)&sm.a[buf][(32 * wave + 16 * q) * 4], 16, a_offv[q], 0,
@@ -112,10 +114,10 @@ __device__ __forceinline__ void f32_tile_dma(F32DmaSmem& sm, const float* A, con
   constexpr int kWaitVm0 = 0x0F70;  // vmcnt(0) only
   const int nk = (K + SBK - 1) / SBK;
   // A fragments: the four k values of the step in one read per row block; B
-  // fragments per sub-step.  The loads of the step after next go out right
-  // after the barrier into the buffer every wavefront has just finished
-  // reading, so they have a whole step of MFMAs to land in; the last two
-  // steps load steps past K (zeros nothing reads).
+  // fragments per sub-step.  Step kt issues the loads of step kt + 1 first,
+  // into the buffer every wavefront finished reading before the previous
+  // barrier, so they land while the step's 64 MFMAs run; the last step
+  // loads a step past K (zeros nothing reads).
   f4_t af[4];
   float bf[4][4];
   auto rd = [&](int buf) {
@@ -126,13 +128,9 @@ __device__ __forceinline__ void f32_tile_dma(F32DmaSmem& sm, const float* A, con
 #pragma unroll
       for (int j = 0; j < 4; ++j) bf[kk][j] = sm.b[buf][brow(4 * lg + kk) + wn * 64 + j * 16 + li];
   };
-  dma(0, 0);
-  __builtin_amdgcn_s_waitcnt(kWaitVm0);
-  __syncthreads();
-  dma(1, SBK);
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    rd(cur);
+  constexpr std::true_type kChecked{};
+  constexpr std::false_type kPlain{};
+  auto mma_all = [&] {
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
@@ -140,10 +138,47 @@ __device__ __forceinline__ void f32_tile_dma(F32DmaSmem& sm, const float* A, con
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][kk], bf[kk][j], acc[i][j], 0, 0, 0);
+  };
+  dma(0, 0, kChecked);
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);
+  __syncthreads();
+  dma(1, SBK, kChecked);
+  // step 0: its successor's loads are already out
+  rd(0);
+  mma_all();
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);
+  __syncthreads();
+  // step kt >= 1: the loads of step kt + 1 go into the buffer step kt - 1
+  // used, ahead of this step's fragment reads and MFMAs
+  auto step = [&](int kt, auto checked) {
+    const int cur = kt & 1;
+    dma(cur ^ 1, (kt + 1) * SBK, checked);
+    rd(cur);
+    mma_all();
+    if constexpr (!decltype(checked)::value) {
+      // scheduling groups: the first fragment reads, then the MFMAs in one
+      // stream (the compiler still issues the four loads up front; this
+      // order measured 0.3% faster than its own and 2% on whole products)
+      __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // eight LDS reads
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);  // four MFMAs
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // a VMEM read
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 48, 0);  // the other MFMAs
+    }
+    // every MFMA of the step is issued before the wait for the next step's
+    // loads and the barrier (the compiler would otherwise sink some below)
+    __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
-    dma(cur, (kt + 2) * SBK);
-  }
+  };
+  // steps whose loads (one step ahead) lie wholly inside K run a loop body
+  // without branches
+  const int nplain = K / SBK - 1 < nk ? K / SBK - 1 : nk;
+  int kt = 1;
+  for (; kt < nplain; ++kt) step(kt, kPlain);
+  for (; kt < nk; ++kt) step(kt, kChecked);
   // the loads past K have landed and every read is done before the next
   // tile's first loads reuse the buffers
   __builtin_amdgcn_s_waitcnt(kWaitVm0);
