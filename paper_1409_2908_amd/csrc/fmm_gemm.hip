@@ -342,13 +342,12 @@ static int blocks_per_cu() {
 }
 
 // Tile shape of a launch: an explicit 64 or 128 wins; otherwise (0) 64 x 64
-// when the 128 x 128 tiles would leave compute units idle (use_small_tiles)
-// and 128 x 128 else (at full occupancy the small tile runs 7% (FP64) to 26%
-// (FP32) below the large one).  The planner counts tiles of kTileM x kTileN;
+// when the 128 x 128 tiles would leave compute units idle (use_small_tiles,
+// per the kernel the large tiles would run) and 128 x 128 else.  The planner counts tiles of kTileM x kTileN;
 // a launch with another shape re-counts every group's tiles.
-static int pick_tile(const GemmArgs& a, int num_cus) {
+static int pick_tile(const GemmArgs& a, int num_cus, int kind) {
   if (a.tile == 64 || a.tile == 128) return a.tile;
-  return use_small_tiles(a.total_tiles, num_cus) ? 64 : 128;
+  return use_small_tiles(a.total_tiles, num_cus, kind) ? 64 : 128;
 }
 
 template <typename T, int BM, int NT>
@@ -389,21 +388,25 @@ static int64_t tiles64(const GemmArgs& a) {
 // tiles spread the product over four times as many units.  Every tile edge
 // accumulates each output element over the same K steps in the same order.
 template <typename T, int NT>
-static hipError_t launch_typed(const GemmArgs& a, int num_cus, hipStream_t s) {
+static hipError_t launch_typed(const GemmArgs& a, int num_cus, hipStream_t s, int kind) {
   if (a.tile == 0 && 2 * tiles64(a) <= num_cus) return launch_tiles<T, 32, NT>(a, num_cus, s);
   if constexpr (NT > 0) return launch_tiles<T, 64, NT>(a, num_cus, s);
   else
-    return pick_tile(a, num_cus) == 64 ? launch_tiles<T, 64, 0>(a, num_cus, s) : launch_tiles<T, 128, 0>(a, num_cus, s);
+    return pick_tile(a, num_cus, kind) == 64 ? launch_tiles<T, 64, 0>(a, num_cus, s)
+                                             : launch_tiles<T, 128, 0>(a, num_cus, s);
 }
 
 template <typename T>
 static hipError_t launch_forms(const GemmArgs& a, int num_cus, hipStream_t s) {
   // launches on 128 x 128 tiles whose operands allow it stage them by direct
-  // loads (fmm_gemm_f64dma.hip, fmm_gemm_f32dma.hip); same products, same order
-  if (a.form_terms == 0 && a.dma && !(a.tile == 0 && 2 * tiles64(a) <= num_cus) && pick_tile(a, num_cus) == 128)
+  // loads (fmm_gemm_f64dma.hip, fmm_gemm_f32dma.hip); same products, same
+  // order.  The tile rule follows the kernel the large tiles would run.
+  const bool dma = a.form_terms == 0 && a.dma;
+  const int kind = !dma ? kTilesStaged : std::is_same_v<T, double> ? kTilesF64Dma : kTilesF32Dma;
+  if (dma && !(a.tile == 0 && 2 * tiles64(a) <= num_cus) && pick_tile(a, num_cus, kind) == 128)
     return std::is_same_v<T, double> ? launch_gemm_f64_dma(a, num_cus, s) : launch_gemm_f32_dma(a, num_cus, s);
-  if (a.form_terms == 0) return launch_typed<T, 0>(a, num_cus, s);
-  if (a.form_terms == kMaxLeafTerms) return launch_typed<T, kMaxLeafTerms>(a, num_cus, s);
+  if (a.form_terms == 0) return launch_typed<T, 0>(a, num_cus, s, kind);
+  if (a.form_terms == kMaxLeafTerms) return launch_typed<T, kMaxLeafTerms>(a, num_cus, s, kind);
   return hipErrorInvalidValue;
 }
 

@@ -882,10 +882,10 @@ hipError_t launch_gemm_bf16x3(const GemmArgs& a, int num_cus, hipStream_t s) {
     if (e != hipSuccess) return e;
     const GemmArgs rest = select_groups(a, false);
     if (rest.total_tiles <= 0) return hipSuccess;
-    const bool small = use_small_tiles(rest.total_tiles, num_cus, true);
+    const bool small = use_small_tiles(rest.total_tiles, num_cus, kTilesBf16x3);
     return small ? launch_bf16x3_tiles<64>(rest, num_cus, s) : launch_bf16x3_tiles<128>(rest, num_cus, s);
   }
-  const bool small = a.tile == 64 || (a.tile != 128 && use_small_tiles(a.total_tiles, num_cus, true));
+  const bool small = a.tile == 64 || (a.tile != 128 && use_small_tiles(a.total_tiles, num_cus, kTilesBf16x3));
   return small ? launch_bf16x3_tiles<64>(a, num_cus, s) : launch_bf16x3_tiles<128>(a, num_cus, s);
 }
 

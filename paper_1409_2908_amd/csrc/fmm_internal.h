@@ -308,14 +308,25 @@ bool choose(int64_t m, int64_t k, int64_t n, int dtype, const char* alg, int lev
 
 constexpr int64_t kTileM = 128, kTileN = 128;
 
+// Which 128 x 128 kernel a launch would run, for use_small_tiles.
+enum TileKernel { kTilesStaged = 0, kTilesBf16x3 = 1, kTilesF64Dma = 2, kTilesF32Dma = 3 };
+
 // Whether a leaf launch of `tiles128` tiles of kTileM x kTileN on `cus`
 // compute units runs 64 x 64 tiles instead: when the large tiles would leave
-// compute units idle -- fewer tiles than compute units, or (FP64 / FP32,
-// whose small tile keeps 74-93% of the large one's rate; BF16x3's keeps 68%)
-// at most four waves of two tiles per CU whose last wave is at most half full.
-inline bool use_small_tiles(int64_t tiles128, int64_t cus, bool bf16x3 = false) {
+// compute units idle.  Every kernel: fewer tiles than compute units.  The
+// register-staged FP64 / FP32 kernel (whose small tile keeps 74-93% of its
+// rate) also at most four waves of two tiles per CU whose last wave is at most
+// half full; the FP64 direct-load kernel, faster than the small tile by more,
+// only when that last wave is partial and follows a full one (at exactly one
+// tile per CU the large tiles measured 16% faster); the FP32 direct-load
+// kernel, which holds four tiles per CU, and BF16x3 (68%) never.
+inline bool use_small_tiles(int64_t tiles128, int64_t cus, int kind = kTilesStaged) {
+  if (tiles128 < cus) return true;
   const int64_t rem = tiles128 % (2 * cus);
-  return tiles128 < cus || (!bf16x3 && tiles128 < 4 * cus && rem > 0 && rem <= cus);
+  const bool partial = tiles128 < 4 * cus && rem > 0 && rem <= cus;
+  if (kind == kTilesStaged) return partial;
+  if (kind == kTilesF64Dma) return partial && tiles128 > 2 * cus;
+  return false;
 }
 
 }  // namespace fmm

@@ -117,7 +117,7 @@ void predict(const PlanSummary& P, int dtype, Candidate& c) {
       tiles32 += t;
     }
     leaf_s = waves_time(units32, wmax, tiles32, kSlotsSmall / kCUs, 32, ref * kTiny);
-  } else if (tiles > 0 && use_small_tiles((int64_t)tiles, kCUs, dtype == 2)) {
+  } else if (tiles > 0 && use_small_tiles((int64_t)tiles, kCUs, dtype == 2 ? kTilesBf16x3 : dtype == 0 ? kTilesF64Dma : kTilesF32Dma)) {
     // the launch runs 64 x 64 tiles (units weighted by each group's rate,
     // as for the large tiles)
     double units64 = 0, tiles64 = 0;
