@@ -150,37 +150,42 @@ template <int ID, int SIDE>
 __constant__ ColTable<ID, SIDE> kColTable = make_col_table<ID, SIDE>();
 
 // Two levels of operand formation in one pass for wide base cases, staged
-// through LDS.  A workgroup owns 64 consecutive columns q of one row p of
-// the leaf-sized grid: it first loads the NB^2 source elements of those 64
-// positions into LDS (every load instruction of a wavefront reads 512
-// contiguous bytes and a thread has NB^2 / 4 loads in flight), then each
-// wavefront takes every fourth top-level output r1, forms the NB level-two
-// sums y[i2] = sum_i1 U[i1][r1] x[i1][i2] from LDS, and writes
-// S_{r1,r2} = sum_i2 U[i2][r2] y[i2] for every r2.  Sums run in ascending
-// index order from -0.0 with fused multiply-adds: with coefficients +-2^e the
-// first step returns c*x exactly and every later one rounds like the
-// corresponding add or subtract of the chain, so the results equal the
-// register kernel's bit for bit.
-template <int ID, int SIDE>
+// through LDS.  A workgroup owns 64 * NP consecutive columns q of one row p
+// of the leaf-sized grid, NP adjacent ones per lane: it first loads the NB^2
+// source elements of those positions into LDS (a thread has NP * NB^2 / 4
+// loads in flight), then each wavefront takes every fourth top-level output
+// r1, forms the NB level-two sums y[i2] = sum_i1 U[i1][r1] x[i1][i2] from
+// LDS, and writes S_{r1,r2} = sum_i2 U[i2][r2] y[i2] for every r2 (with NP =
+// 2 and FP64 outputs one 16-byte store per lane, 1 KB per wavefront).  Sums
+// run in ascending index order from -0.0 with fused multiply-adds: with
+// coefficients +-2^e the first step returns c*x exactly and every later one
+// rounds like the corresponding add or subtract of the chain, so the results
+// equal the register kernel's bit for bit, for either NP.
+template <int ID, int SIDE, int NP>
 __global__ void __launch_bounds__(256) form2_kernel(FormArgs a) {
   using S = Side<ID, SIDE>;
   constexpr int NB = S::NB, R = S::R, BR = S::BR, BC = S::BC, NIN = NB * NB;
-  __shared__ double xs[NIN][64];
+  __shared__ double xs[NIN][64 * NP];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t q = (int64_t)blockIdx.x * (64 * NP) + NP * lane;
   const int64_t p = blockIdx.y;
   const int g = blockIdx.z;
-  const bool valid = q < a.w;
   const Ref src = a.groups[g];
   int64_t ld;
   const char* base = buf_ptr(a.bases, src, &ld);
   const int64_t h = a.h, w = a.w;
-  // Branch-free loads, all in flight before the first LDS store: lanes past
-  // the last column read column w - 1 and store 0.
-  const int64_t qc = valid ? q : w - 1;
+  // Branch-free loads, all in flight before the first LDS store: positions
+  // past the last column read column w - 1 and store 0.
+  bool ok[NP];
+  int64_t qc[NP];
+#pragma unroll
+  for (int e = 0; e < NP; ++e) {
+    ok[e] = q + e < w;
+    qc[e] = ok[e] ? q + e : w - 1;
+  }
   constexpr int NJ = (NIN + 3) / 4;
-  double v[NJ];
+  double v[NJ][NP];
   auto load_all = [&](auto tag) {
     using T = decltype(tag);
     const T* bp = (const T*)base + src.off;
@@ -190,38 +195,63 @@ __global__ void __launch_bounds__(256) form2_kernel(FormArgs a) {
       const int i1 = idx / NB, i2 = idx % NB;
       const int a1 = i1 / BC, b1 = i1 % BC, a2 = i2 / BC, b2 = i2 % BC;
       const int64_t row = src.row + (a1 * BR + a2) * h + p;
-      const int64_t col = src.col + (b1 * BC + b2) * w + qc;
-      v[k] = (double)bp[row * ld + col];
+      const int64_t col = src.col + (b1 * BC + b2) * w;
+#pragma unroll
+      for (int e = 0; e < NP; ++e) v[k][e] = (double)bp[row * ld + col + qc[e]];
     }
   };
   if (src.elt == ELT_F64) load_all(double{});
   else load_all(float{});
 #pragma unroll
   for (int k = 0; k < NJ; ++k)
-    if (wave + 4 * k < NIN) xs[wave + 4 * k][lane] = valid ? v[k] * src.alpha : 0.0;
+    if (wave + 4 * k < NIN) {
+#pragma unroll
+      for (int e = 0; e < NP; ++e) xs[wave + 4 * k][NP * lane + e] = ok[e] ? v[k][e] * src.alpha : 0.0;
+    }
   __syncthreads();
-  if (!valid) return;
+  if (!ok[0]) return;
   char* ws = (char*)a.bases.ptr[BUF_WS];
   const int64_t* outs = a.outs + (int64_t)g * a.nout;
   const int64_t pos = p * a.out_ld + q;
   const ColTable<ID, SIDE>& tab = kColTable<ID, SIDE>;
+  // both positions of a lane in one 16-byte store: FP64 outputs, the pair
+  // inside the row and 16-byte aligned (workspace outputs start 256-byte
+  // aligned, so an even row length and an even q make it so)
+  const bool pair = NP == 2 && ok[NP - 1] && a.out_elt == ELT_F64 && (a.out_ld & 1) == 0;
   for (int r1 = wave; r1 < R; r1 += 4) {
-    double y[NB];
+    double y[NP][NB];
 #pragma unroll
     for (int i2 = 0; i2 < NB; ++i2) {
-      double acc = -0.0;
+      double acc[NP];
+#pragma unroll
+      for (int e = 0; e < NP; ++e) acc[e] = -0.0;
 #pragma unroll
       for (int i1 = 0; i1 < NB; ++i1) {
         const int c = tab.c[r1][i1];
-        if (c != 0) acc = __fma_rn((double)c, xs[i1 * NB + i2][lane], acc);
+        if (c != 0) {
+#pragma unroll
+          for (int e = 0; e < NP; ++e) acc[e] = __fma_rn((double)c, xs[i1 * NB + i2][NP * lane + e], acc[e]);
+        }
       }
-      y[i2] = acc;
+#pragma unroll
+      for (int e = 0; e < NP; ++e) y[e][i2] = acc[e];
     }
     const int64_t* o = outs + r1 * R;
     static_for<0, R>([&](auto r2c) {
       constexpr int r2 = decltype(r2c)::value;
       const int64_t off = o[r2];
-      if (off >= 0) store_out(ws, a.out_elt, off + pos, a.out_plane, chain_col<S, r2, 1, NB>(y));
+      if (off < 0) return;
+      if constexpr (NP == 2) {
+        const double s0 = chain_col<S, r2, 1, NB>(y[0]), s1 = chain_col<S, r2, 1, NB>(y[1]);
+        if (pair && ((off + pos) & 1) == 0) {
+          *(double2*)((double*)ws + off + pos) = make_double2(s0, s1);
+        } else {
+          store_out(ws, a.out_elt, off + pos, a.out_plane, s0);
+          if (ok[1]) store_out(ws, a.out_elt, off + pos + 1, a.out_plane, s1);
+        }
+      } else {
+        store_out(ws, a.out_elt, off + pos, a.out_plane, chain_col<S, r2, 1, NB>(y[0]));
+      }
     });
   }
 }
@@ -491,9 +521,14 @@ hipError_t launch_form_id(const FormArgs& a, int side, int lv, int ngroups, hipS
   // operands (k-octet layout), which keep the register kernel's 8 x 8 mapping.
   if constexpr (kFuse2<ID>) {
     if (lv == 2 && Alg<ID>::R > 8 && !(side == 1 && a.out_elt == ELT_BF16X2)) {
-      dim3 g2((unsigned)((a.w + 63) / 64), (unsigned)a.h, (unsigned)ngroups);
-      if (side == 0) hipLaunchKernelGGL((form2_kernel<ID, 0>), g2, dim3(256), 0, s, a);
-      else hipLaunchKernelGGL((form2_kernel<ID, 1>), g2, dim3(256), 0, s, a);
+      // two positions per lane while the staged sources of 128 positions fit
+      // two workgroups in a compute unit's LDS (at most 8 blocks per side:
+      // 64 KB); measured 2-3% faster per pass on <4,2,4> at 16384^3
+      constexpr bool two = Alg<ID>::M * Alg<ID>::K <= 8 && Alg<ID>::K * Alg<ID>::N <= 8;
+      constexpr int NP = two ? 2 : 1;
+      dim3 g2((unsigned)((a.w + 64 * NP - 1) / (64 * NP)), (unsigned)a.h, (unsigned)ngroups);
+      if (side == 0) hipLaunchKernelGGL((form2_kernel<ID, 0, NP>), g2, dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((form2_kernel<ID, 1, NP>), g2, dim3(256), 0, s, a);
       return hipGetLastError();
     }
   }
