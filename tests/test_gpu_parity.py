@@ -308,6 +308,42 @@ def test_leaf_tile_shapes_agree(F, dtype_name, alg, L, shape):
 
 
 
+@pytest.mark.parametrize("dtype_name,alg,L,shape", [
+    ("F64", "classical", 0, (258, 1002, 390)),
+    ("F64", "strassen_222_7", 1, (516, 1000, 772)),
+    ("F64", "fmm_424_26", 1, (1032, 1004, 1032)),
+    ("F32", "classical", 0, (260, 1004, 388)),
+    ("F32", "strassen_222_7", 1, (520, 1000, 776)),
+    ("F32", "fmm_424_26", 1, (1032, 1000, 1040)),
+])
+def test_direct_load_leaf_edges(F, dtype_name, alg, L, shape):
+    """Shapes whose operands satisfy the direct-load kernels' alignment (FP64:
+    even leading dimensions and K, N; FP32: multiples of 4, 16-byte rows), so
+    leaf_tile 128 runs gemm_f64_dma_kernel / gemm_f32_dma_kernel, with partial
+    128-row and 128-column tiles and a K tail that is not a multiple of the
+    16-k step (10, 4, 6, 12, 4, 8 here).  The direct-load tiles must agree
+    bit for bit with the register-staged 64 x 64 tiles and match the oracle."""
+    dtype = getattr(F, dtype_name)
+    np_dt = np.float64 if dtype_name == "F64" else np.float32
+    m, k, n = shape
+    say(f"case direct-load edges {dtype_name} {alg} L={L} {m}x{k}x{n}")
+    A, B = fmm_inputs.operands(23, m, k, n, "uniform", np_dt)
+    out = {}
+    for tile in (128, 64, 0):
+        with F.Plan(alg, m, k, n, L, dtype, leaf_tile=tile) as p:
+            out[tile] = to_host(p.multiply(to_dev(A), to_dev(B)))
+    ref = classical.gemm(A, B)
+    tol = 1e-12 if dtype_name == "F64" else 2e-6 * 2 ** L
+    assert relf(out[128], ref) <= tol
+    iv = np.int64 if dtype_name == "F64" else np.int32
+    assert np.array_equal(out[128].view(iv), out[64].view(iv))
+    assert np.array_equal(out[0].view(iv), out[64].view(iv))
+    Ai, Bi = fmm_inputs.operands(24, m, k, n, "integer", np_dt)
+    with F.Plan(alg, m, k, n, L, dtype, leaf_tile=128) as p:
+        Ci = to_host(p.multiply(to_dev(Ai), to_dev(Bi)))
+    assert np.array_equal(Ci.astype(np.float64), classical.gemm(Ai.astype(np.float64), Bi.astype(np.float64)))
+
+
 def test_fp64_error_per_depth(F):
     """The error of each square-configuration base case per depth at 4096^3
     (uniform inputs; 32 sampled rows, every top-level block boundary among
