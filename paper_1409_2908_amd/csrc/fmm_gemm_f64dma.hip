@@ -8,8 +8,8 @@
 // from memory to LDS with buffer_load_dwordx4 ... lds, which writes the 16
 // bytes of lane i of a wavefront at byte 16 i of the instruction's 1 KB LDS
 // chunk.  No registers hold staged data and no LDS store instructions are
-// issued, so the wavefronts issue only fragment reads and MFMAs between
-// barriers.
+// issued: between barriers the wavefronts issue only the direct loads,
+// fragment reads and MFMAs.
 //
 // Layouts.  A: row r of the tile holds its 16 k as 8 slots of one k pair
 // (16 bytes); k pair p sits in slot p ^ ((r >> 1) & 7), so a chunk is 8 rows
