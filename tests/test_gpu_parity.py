@@ -163,6 +163,48 @@ def test_operand_formation_bit_exact(F, alg, L, fuse, mult, monkeypatch):
                 assert np.array_equal(got.view(np.int64), ref[leaf].view(np.int64)), (side, leaf)
 
 
+@pytest.mark.parametrize("alg,L,shape,dtype_name", [
+    ("fmm_424_26", 2, (592, 524, 2064), "F64"),     # leaf widths 131 (S) and 129 (T): odd, past one workgroup
+    ("fmm_424_26", 2, (640, 512, 2048), "F64"),     # even widths 128 (S, T): every pair stored at once
+    ("fmm_423_20", 2, (400, 260, 873), "F64"),      # leaf widths 65 and 97
+    ("strassen_222_7", 2, (520, 1036, 772), "F32"),  # FP32 outputs, two positions per thread: widths 259, 193
+    ("strassen_222_7", 1, (518, 1030, 774), "F32"),  # one level: widths 515, 387
+])
+def test_two_position_formation_bit_exact(F, alg, L, shape, dtype_name, monkeypatch):
+    """The formation kernels that give a lane or thread two adjacent positions
+    (the two-level LDS pass of base cases with at most 8 blocks per side, and
+    the register pass for FP32 outputs) on widths that are odd, a multiple
+    of the workgroup's 128 positions, or past it: every leaf operand equals
+    the oracle's chain bit for bit (FP32 outputs: the binary64 chain rounded
+    once to binary32)."""
+    monkeypatch.setenv("FMM_FUSE", str(L))
+    a = algorithms.get(alg)
+    m, k, n = shape
+    np_dt = np.float64 if dtype_name == "F64" else np.float32
+    say(f"case two-position form {alg} L={L} {dtype_name} m={m} k={k} n={n}")
+    A, B = fmm_inputs.operands(7, m, k, n, "uniform", np_dt)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    fm, fk, fn = a.M ** L, a.K ** L, a.N ** L
+    assert m % fm == 0 and k % fk == 0 and n % fn == 0
+    S = recursive.form_operands(a, L, A64, "A")
+    T = recursive.form_operands(a, L, B64, "B")
+    with F.Plan(alg, m, k, n, L, getattr(F, dtype_name)) as p:
+        info = p.info
+        dA, dB = to_dev(A), to_dev(B)
+        C = p.run_stage(F.STAGE_FORM_S, dA, dB)
+        p.run_stage(F.STAGE_FORM_T, dA, dB, C)
+        lm, lk, ln = info["leaf_m"], info["leaf_k"], info["leaf_n"]
+        iv = np.int64 if dtype_name == "F64" else np.int32
+        for side, X, ref, (h, w) in ((0, A, S, (lm, lk)), (1, B, T, (lk, ln))):
+            for leaf in range(a.R ** L):
+                loc, off, row, col, ld, alpha = p.operand(side, leaf)
+                if loc != F.LOC_WORKSPACE:
+                    continue
+                got = ws_read(p, off, h, w, ld, np_dt) * np_dt(alpha)
+                want = ref[leaf].astype(np_dt)
+                assert np.array_equal(got.view(iv), want.view(iv)), (side, leaf)
+
+
 @pytest.mark.parametrize("alg,L,fuse", [("strassen_222_7", 1, "1"), ("strassen_222_7", 2, "2"),
                                         ("fmm_424_26", 2, "2"), ("fmm_424_26", 2, "1"),
                                         ("fmm_333_23", 1, "1"), ("strassen_222_7", 3, "2")])
