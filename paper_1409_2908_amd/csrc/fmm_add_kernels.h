@@ -119,19 +119,18 @@ __global__ void __launch_bounds__(kAddTX * kAddTY) form_kernel(FormArgs a) {
 // the pair is aligned.  Same chains, same order.  The launcher runs it for
 // FP32 outputs, where it measured 4-5% faster per pass (Strassen L=2 at
 // 16384^3: 1.31 -> 1.25 ms); for FP64 outputs it measured 3% slower.
-template <int ID, int SIDE, int LV>
-__global__ void __launch_bounds__(kAddTX * kAddTY) form2p_kernel(FormArgs a) {
+// PAIRS: FP32 source and FP32 outputs with every pair 8-byte aligned (even
+// offsets, columns, widths and leading dimensions, an 8-byte aligned source
+// pointer): each pair is one 8-byte load and one 8-byte store, with no
+// run-time element-type or alignment test per access.
+template <int ID, int SIDE, int LV, bool PAIRS>
+__device__ __forceinline__ void form2p_body(const FormArgs& a, const Ref& src, const char* base, int64_t ld,
+                                            int64_t p, int64_t q) {
   using S = Side<ID, SIDE>;
   constexpr int NB = S::NB, R = S::R, BR = S::BR, BC = S::BC;
   constexpr int NIN = LV == 1 ? NB : NB * NB;
-  const int64_t q = ((int64_t)blockIdx.x * kAddTX + threadIdx.x) * 2;
-  const int64_t p = (int64_t)blockIdx.y * kAddTY + threadIdx.y;
-  if (q >= a.w || p >= a.h) return;
-  const bool two = q + 1 < a.w;
+  const bool two = PAIRS || q + 1 < a.w;
   const int g = (int)blockIdx.z;
-  const Ref src = a.groups[g];
-  int64_t ld;
-  const char* base = buf_ptr(a.bases, src, &ld);
   const int64_t h = a.h, w = a.w;
   double x0[NIN], x1[NIN];
   static_for<0, NIN>([&](auto ic) {
@@ -142,8 +141,14 @@ __global__ void __launch_bounds__(kAddTX * kAddTY) form2p_kernel(FormArgs a) {
     const int64_t row = src.row + (LV == 1 ? a1 * h : (a1 * BR + a2) * h) + p;
     const int64_t col = src.col + (LV == 1 ? b1 * w : (b1 * BC + b2) * w) + q;
     const int64_t e = src.off + row * ld + col;
-    x0[idx] = load_elt(base, src.elt, e) * src.alpha;
-    x1[idx] = load_elt(base, src.elt, two ? e + 1 : e) * src.alpha;
+    if constexpr (PAIRS) {
+      const float2 v = *(const float2*)((const float*)base + e);
+      x0[idx] = (double)v.x * src.alpha;
+      x1[idx] = (double)v.y * src.alpha;
+    } else {
+      x0[idx] = load_elt(base, src.elt, e) * src.alpha;
+      x1[idx] = load_elt(base, src.elt, two ? e + 1 : e) * src.alpha;
+    }
   });
   char* ws = (char*)a.bases.ptr[BUF_WS];
   const int64_t* outs = a.outs + (int64_t)g * a.nout;
@@ -151,7 +156,14 @@ __global__ void __launch_bounds__(kAddTX * kAddTY) form2p_kernel(FormArgs a) {
   const bool f64 = a.out_elt == ELT_F64;
   auto put = [&](int64_t off, double v0, double v1) {
     const int64_t i = off + pos;
-    if (two && (i & 1) == 0) {
+    if constexpr (PAIRS) {
+      if ((off & 1) == 0) {  // uniform: the pair's parity is the offset's
+        *(float2*)((float*)ws + i) = make_float2((float)v0, (float)v1);
+      } else {
+        ((float*)ws)[i] = (float)v0;
+        ((float*)ws)[i + 1] = (float)v1;
+      }
+    } else if (two && (i & 1) == 0) {
       if (f64) *(double2*)((double*)ws + i) = make_double2(v0, v1);
       else *(float2*)((float*)ws + i) = make_float2((float)v0, (float)v1);
     } else {
@@ -181,6 +193,22 @@ __global__ void __launch_bounds__(kAddTX * kAddTY) form2p_kernel(FormArgs a) {
       });
     });
   }
+}
+
+template <int ID, int SIDE, int LV>
+__global__ void __launch_bounds__(kAddTX * kAddTY) form2p_kernel(FormArgs a) {
+  const int64_t q = ((int64_t)blockIdx.x * kAddTX + threadIdx.x) * 2;
+  const int64_t p = (int64_t)blockIdx.y * kAddTY + threadIdx.y;
+  if (q >= a.w || p >= a.h) return;
+  const Ref src = a.groups[blockIdx.z];
+  int64_t ld;
+  const char* base = buf_ptr(a.bases, src, &ld);
+  // every value below is uniform over the launch's group
+  const bool pairs = a.out_elt == ELT_F32 && src.elt == ELT_F32 &&
+                     ((src.off | src.col | ld | a.w | a.out_ld) & 1) == 0 &&
+                     ((uintptr_t)base & 7) == 0;
+  if (pairs) form2p_body<ID, SIDE, LV, true>(a, src, base, ld, p, q);
+  else form2p_body<ID, SIDE, LV, false>(a, src, base, ld, p, q);
 }
 
 // One level of S and of T in a single launch, for small problems where the
@@ -334,29 +362,19 @@ __global__ void __launch_bounds__(256) form2_kernel(FormArgs a) {
 // (p + 1, q) of one octet, a wavefront covering 16 columns of one octet (256
 // contiguous bytes per plane, 1 KB per workgroup).  Same chains, in the same
 // order, as form_kernel.
-template <int ID, int SIDE, int LV>
-__global__ void __launch_bounds__(256) form_split2_kernel(FormArgs a) {
+// F32IN: an FP32 source, read without a run-time element-type test; for S
+// operands (pairs along a row) with every pair 8-byte aligned, as one 8-byte
+// load per pair.
+template <int ID, int SIDE, int LV, bool F32IN>
+__device__ __forceinline__ void form_split2_body(const FormArgs& a, const Ref& src, const char* base, int64_t ld,
+                                                 int64_t p, int64_t q) {
   using S = Side<ID, SIDE>;
   constexpr int NB = S::NB, R = S::R, BR = S::BR, BC = S::BC;
   constexpr int NIN = LV == 1 ? NB : NB * NB;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int64_t p, q;
   constexpr int dp = SIDE == 0 ? 0 : 1, dq = SIDE == 0 ? 1 : 0;
-  if constexpr (SIDE == 0) {
-    // blockIdx.x enumerates (row, 512-column block) pairs, rows outer
-    const int64_t ncb = (a.w + 511) / 512;
-    p = (int64_t)blockIdx.x / ncb;
-    q = ((int64_t)blockIdx.x % ncb * 256 + threadIdx.x) * 2;
-  } else {
-    q = (int64_t)blockIdx.x * 64 + wave * 16 + (lane >> 2);
-    p = (int64_t)blockIdx.y * 8 + 2 * (lane & 3);
-  }
-  if (q >= a.w || p >= a.h) return;
-  const bool two = q + dq < a.w && p + dp < a.h;
+  constexpr bool kPairLoad = F32IN && SIDE == 0;
+  const bool two = kPairLoad || (q + dq < a.w && p + dp < a.h);
   const int g = blockIdx.z;
-  const Ref src = a.groups[g];
-  int64_t ld;
-  const char* base = buf_ptr(a.bases, src, &ld);
   const int64_t h = a.h, w = a.w;
   double x0[NIN], x1[NIN];
   static_for<0, NIN>([&](auto ic) {
@@ -367,8 +385,18 @@ __global__ void __launch_bounds__(256) form_split2_kernel(FormArgs a) {
     const int64_t row = src.row + (LV == 1 ? a1 * h : (a1 * BR + a2) * h) + p;
     const int64_t col = src.col + (LV == 1 ? b1 * w : (b1 * BC + b2) * w) + q;
     const int64_t e = src.off + row * ld + col;
-    x0[idx] = load_elt(base, src.elt, e) * src.alpha;
-    x1[idx] = load_elt(base, src.elt, two ? e + dp * ld + dq : e) * src.alpha;
+    if constexpr (kPairLoad) {
+      const float2 v = *(const float2*)((const float*)base + e);
+      x0[idx] = (double)v.x * src.alpha;
+      x1[idx] = (double)v.y * src.alpha;
+    } else if constexpr (F32IN) {
+      const float* bf = (const float*)base;
+      x0[idx] = (double)bf[e] * src.alpha;
+      x1[idx] = (double)bf[two ? e + dp * ld + dq : e] * src.alpha;
+    } else {
+      x0[idx] = load_elt(base, src.elt, e) * src.alpha;
+      x1[idx] = load_elt(base, src.elt, two ? e + dp * ld + dq : e) * src.alpha;
+    }
   });
   unsigned short* ws = (unsigned short*)a.bases.ptr[BUF_WS];
   const int64_t* outs = a.outs + (int64_t)g * a.nout;
@@ -408,6 +436,31 @@ __global__ void __launch_bounds__(256) form_split2_kernel(FormArgs a) {
       });
     });
   }
+}
+
+template <int ID, int SIDE, int LV>
+__global__ void __launch_bounds__(256) form_split2_kernel(FormArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t p, q;
+  if constexpr (SIDE == 0) {
+    // blockIdx.x enumerates (row, 512-column block) pairs, rows outer
+    const int64_t ncb = (a.w + 511) / 512;
+    p = (int64_t)blockIdx.x / ncb;
+    q = ((int64_t)blockIdx.x % ncb * 256 + threadIdx.x) * 2;
+  } else {
+    q = (int64_t)blockIdx.x * 64 + wave * 16 + (lane >> 2);
+    p = (int64_t)blockIdx.y * 8 + 2 * (lane & 3);
+  }
+  if (q >= a.w || p >= a.h) return;
+  const Ref src = a.groups[blockIdx.z];
+  int64_t ld;
+  const char* base = buf_ptr(a.bases, src, &ld);
+  // uniform over the launch's group
+  const bool f32 = src.elt == ELT_F32;
+  const bool pairs = SIDE == 0 ? f32 && ((src.off | src.col | ld | a.w) & 1) == 0 && ((uintptr_t)base & 7) == 0
+                               : f32;
+  if (pairs) form_split2_body<ID, SIDE, LV, true>(a, src, base, ld, p, q);
+  else form_split2_body<ID, SIDE, LV, false>(a, src, base, ld, p, q);
 }
 
 // W-combination, one level: C_k = sum_r W[k][r] M_r at each position.
