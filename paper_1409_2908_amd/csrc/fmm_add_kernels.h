@@ -512,6 +512,87 @@ constexpr WTable<ID> make_w_table() {
 template <int ID>
 __constant__ WTable<ID> kWTable = make_w_table<ID>();
 
+// W-combination, two levels fused, for narrow base cases (R <= 8) with FP32
+// products and FP32 outputs whose pairs of adjacent positions are all 8-byte
+// aligned (the host sets CombineArgs::pairs), in registers: each thread owns
+// positions (p, q) and (p, q + 1) of one row, reads its R^2 products there
+// with one 8-byte load each, and accumulates every C_{c1,c2} with the same
+// FMAs in the same order as combine2_kernel (Y_{r1,c2} from -0.0 over
+// ascending r2, then C_{c1,c2} over ascending r1), so the two agree bit for
+// bit; each output pair is one 8-byte store.  A scheduling fence between
+// consecutive r1 keeps each r1's seven loads together (130 registers, three
+// wavefronts per SIMD).
+template <int ID>
+__global__ void __launch_bounds__(kAddTX * kAddTY) combine2p_kernel(CombineArgs a) {
+  using CB = Comb<ID>;
+  constexpr int R = CB::R, MN = CB::MN, N = Alg<ID>::N, M = Alg<ID>::M;
+  const int64_t q = ((int64_t)blockIdx.x * kAddTX + threadIdx.x) * 2;
+  const int64_t p = (int64_t)blockIdx.y * kAddTY + threadIdx.y;
+  if (q >= a.w || p >= a.h) return;
+  const int g = blockIdx.z;
+  const float* ws = (const float*)a.bases.ptr[BUF_WS];
+  const int64_t gbase = a.in_off[g] + p * a.in_ld + q;
+  double acc0[MN][MN], acc1[MN][MN];
+  static_for<0, MN>([&](auto c1c) {
+    static_for<0, MN>([&](auto c2c) {
+      acc0[decltype(c1c)::value][decltype(c2c)::value] = -0.0;
+      acc1[decltype(c1c)::value][decltype(c2c)::value] = -0.0;
+    });
+  });
+  static_for<0, R>([&](auto r1c) {
+    constexpr int r1 = decltype(r1c)::value;
+    double m0[R], m1[R];
+    static_for<0, R>([&](auto r2c) {
+      constexpr int r2 = decltype(r2c)::value;
+      const float2 v = *(const float2*)(ws + gbase + (int64_t)(r1 * R + r2) * a.in_stride);
+      m0[r2] = v.x;
+      m1[r2] = v.y;
+    });
+    double y0[MN], y1[MN];
+    static_for<0, MN>([&](auto c2c) {
+      constexpr int c2 = decltype(c2c)::value;
+      double t0 = -0.0, t1 = -0.0;
+      static_for<0, R>([&](auto r2c) {
+        constexpr int r2 = decltype(r2c)::value;
+        constexpr int c = CB::coef(c2, r2);
+        if constexpr (c != 0) {
+          t0 = __fma_rn((double)c, m0[r2], t0);
+          t1 = __fma_rn((double)c, m1[r2], t1);
+        }
+      });
+      y0[c2] = t0;
+      y1[c2] = t1;
+    });
+    static_for<0, MN>([&](auto c1c) {
+      constexpr int c1 = decltype(c1c)::value;
+      constexpr int c = CB::coef(c1, r1);
+      if constexpr (c != 0) {
+        static_for<0, MN>([&](auto c2c) {
+          constexpr int c2 = decltype(c2c)::value;
+          acc0[c1][c2] = __fma_rn((double)c, y0[c2], acc0[c1][c2]);
+          acc1[c1][c2] = __fma_rn((double)c, y1[c2], acc1[c1][c2]);
+        });
+      }
+    });
+    __builtin_amdgcn_sched_barrier(0);
+  });
+  const Ref out = a.out[g];
+  int64_t ld;
+  float* ob = (float*)buf_ptr(a.bases, out, &ld);
+  static_for<0, MN>([&](auto c1c) {
+    constexpr int c1 = decltype(c1c)::value;
+    constexpr int a1 = c1 / N, cc1 = c1 % N;
+    static_for<0, MN>([&](auto c2c) {
+      constexpr int c2 = decltype(c2c)::value;
+      constexpr int a2 = c2 / N, cc2 = c2 % N;
+      const int64_t row = (int64_t)(a1 * M + a2) * a.h + p;
+      const int64_t col = (int64_t)(cc1 * N + cc2) * a.w + q;
+      const int64_t idx = out.off + (out.row + row) * ld + out.col + col;
+      *(float2*)(ob + idx) = make_float2((float)acc0[c1][c2], (float)acc1[c1][c2]);
+    });
+  });
+}
+
 // W-combination, two levels fused, for wide base cases.  A workgroup of four
 // wavefronts owns 64 consecutive positions of one row; wavefront w owns the
 // top-level output blocks c1 = w, w+4, ... and accumulates C_{c1,c2} for
@@ -697,6 +778,14 @@ hipError_t launch_combine_id(const CombineArgs& a, int lv, int ngroups, hipStrea
               (unsigned)ngroups);
     hipLaunchKernelGGL((combine1_kernel<ID>), grid, block, 0, s, a);
   } else if (lv == 2) {
+    if constexpr (Alg<ID>::R <= 8) {
+      if (a.pairs) {  // FP32 products and outputs, aligned pairs: the register kernel
+        dim3 grid((unsigned)((a.w + 2 * kAddTX - 1) / (2 * kAddTX)), (unsigned)((a.h + kAddTY - 1) / kAddTY),
+                  (unsigned)ngroups);
+        hipLaunchKernelGGL((combine2p_kernel<ID>), grid, dim3(kAddTX, kAddTY), 0, s, a);
+        return hipGetLastError();
+      }
+    }
     if constexpr (kFuse2<ID>) {
       dim3 grid((unsigned)((a.w + 63) / 64), (unsigned)a.h, (unsigned)ngroups);
       hipLaunchKernelGGL((combine2_kernel<ID>), grid, dim3(256), 0, s, a);

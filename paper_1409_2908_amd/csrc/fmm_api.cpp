@@ -206,6 +206,21 @@ hipError_t run_leaf(const fmm::Plan& P, const fmm::Bases& b, hipStream_t s) {
   return fmm::launch_gemm(a, P.dtype, num_cus(P.device), s);
 }
 
+// Whether every pair of adjacent positions (p, q), (p, q + 1), q even, of a
+// combination pass is 8-byte aligned in the FP32 products and in the FP32
+// output blocks (the register combination kernel's 8-byte accesses).
+bool combine_pairs_ok(const fmm::CombinePass& cp, const fmm::Bases& b) {
+  if (cp.in_elt != fmm::ELT_F32 || cp.has_p || (cp.w & 1) || ((cp.in_ld | cp.in_stride) & 1)) return false;
+  if (((uintptr_t)b.ptr[fmm::BUF_WS] & 7) != 0) return false;
+  for (int64_t off : cp.in_off)
+    if (off & 1) return false;
+  for (const fmm::Ref& o : cp.out) {
+    const int64_t ld = o.buf == fmm::BUF_WS ? o.ld : b.ld[o.buf];
+    if (o.elt != fmm::ELT_F32 || ((o.off | o.col | ld) & 1) || ((uintptr_t)b.ptr[o.buf] & 7) != 0) return false;
+  }
+  return true;
+}
+
 hipError_t run_combine(const fmm::Plan& P, const fmm::Bases& b, hipStream_t s) {
   for (const fmm::CombinePass& cp : P.w_passes) {
     fmm::CombineArgs a;
@@ -220,6 +235,7 @@ hipError_t run_combine(const fmm::Plan& P, const fmm::Bases& b, hipStream_t s) {
     a.in_elt = cp.in_elt;
     a.has_p = cp.has_p ? 1 : 0;
     a.p = cp.p;
+    a.pairs = combine_pairs_ok(cp, b) ? 1 : 0;
     hipError_t e = fmm::launch_combine(cp.alg, a, cp.lv, cp.ngroups, s);
     if (e != hipSuccess) return e;
   }

@@ -151,6 +151,9 @@ struct CombineArgs {
   int in_elt;
   int has_p;
   Ref p;
+  // set by the host: FP32 products and outputs, no k-peel term, and every
+  // pair of adjacent positions 8-byte aligned in the products and in C
+  int pairs;
 };
 
 // --- plan -----------------------------------------------------------------

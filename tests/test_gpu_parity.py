@@ -169,14 +169,16 @@ def test_operand_formation_bit_exact(F, alg, L, fuse, mult, monkeypatch):
     ("fmm_423_20", 2, (400, 260, 873), "F64"),      # leaf widths 65 and 97
     ("strassen_222_7", 2, (520, 1036, 772), "F32"),  # FP32 outputs, two positions per thread: widths 259, 193
     ("strassen_222_7", 1, (518, 1030, 774), "F32"),  # one level: widths 515, 387
+    ("strassen_222_7", 2, (520, 1032, 776), "F32"),  # even widths 258, 194: 8-byte pair loads and stores
+    ("strassen_222_7", 1, (518, 1028, 772), "F32"),  # even widths 514, 386
 ])
 def test_two_position_formation_bit_exact(F, alg, L, shape, dtype_name, monkeypatch):
     """The formation kernels that give a lane or thread two adjacent positions
     (the two-level LDS pass of base cases with at most 8 blocks per side, and
     the register pass for FP32 outputs) on widths that are odd, a multiple
-    of the workgroup's 128 positions, or past it: every leaf operand equals
-    the oracle's chain bit for bit (FP32 outputs: the binary64 chain rounded
-    once to binary32)."""
+    of the workgroup's 128 positions, or past it (FP32 with even widths: the
+    aligned-pair path): every leaf operand equals the oracle's chain bit for
+    bit (FP32 outputs: the binary64 chain rounded once to binary32)."""
     monkeypatch.setenv("FMM_FUSE", str(L))
     a = algorithms.get(alg)
     m, k, n = shape
@@ -232,6 +234,42 @@ def test_combination_bit_exact(F, alg, L, fuse, monkeypatch):
         got = to_host(C)
     ref = recursive.combine_products(a, L, Ms)
     assert np.array_equal(got.view(np.int64), ref.view(np.int64))
+
+
+@pytest.mark.parametrize("alg,dtype_name,shape", [
+    ("strassen_222_7", "F32", (148, 20, 264)),         # leaf width 66: aligned pairs, one partial workgroup
+    ("strassen_222_7", "F32", (92, 20, 1032)),         # width 258: several workgroups and a partial one
+    ("strassen_222_7", "F32", (148, 20, 260)),         # width 65: odd, the LDS kernel
+    ("strassen_222_7", "F32_BF16X3", (148, 20, 1032)),
+    ("winograd_222_7", "F32", (100, 20, 520)),
+    ("classical_222_8", "F32", (60, 20, 264)),
+])
+def test_fp32_combination_bit_exact(F, alg, dtype_name, shape, monkeypatch):
+    """Two fused levels of the W-combination of seeded FP32 leaf products (the
+    register kernel for aligned pairs, the LDS kernel otherwise) equal the
+    oracle's binary64 chains rounded once to binary32, bit for bit."""
+    monkeypatch.setenv("FMM_FUSE", "2")
+    a = algorithms.get(alg)
+    m, k, n = shape
+    say(f"case fp32 combine {alg} {dtype_name} m={m} k={k} n={n}")
+    with F.Plan(alg, m, k, n, 2, getattr(F, dtype_name)) as p:
+        info = p.info
+        lm, ln = info["leaf_m"], info["leaf_n"]
+        assert (lm * a.M ** 2, ln * a.N ** 2) == (m, n)
+        Ms = []
+        for leaf in range(a.R ** 2):
+            Mv = fmm_inputs.matrix(400 + leaf, 7, lm, ln, "uniform").astype(np.float32)
+            Ms.append(Mv.astype(np.float64))
+            loc, off, row, col, ld, alpha = p.operand(2, leaf)
+            assert loc == F.LOC_WORKSPACE
+            ws_write(p, off, Mv, ld)
+        import torch
+        dA = torch.zeros((m, k), dtype=torch.float32, device="cuda")
+        dB = torch.zeros((k, n), dtype=torch.float32, device="cuda")
+        got = to_host(p.run_stage(F.STAGE_COMBINE, dA, dB))
+    ref = recursive.combine_products(a, 2, Ms).astype(np.float32)
+    assert got.dtype == np.float32
+    assert np.array_equal(got.view(np.int32), ref.view(np.int32))
 
 
 def test_classical_gemm_kernel(F):
