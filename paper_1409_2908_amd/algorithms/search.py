@@ -179,6 +179,85 @@ def lift(M, K, N, scheme, rng, tries=400):
     return None
 
 
+def lift_2adic(M, K, N, scheme, bits=24, bound=4):
+    """Integer coefficients for a GF(2) scheme by Hensel lifting, every entry
+    free (not only the signs on the GF(2) support), or None.
+
+    A solution x modulo 2^e of the Brent equations F(x) = 0 (Equation (2))
+    extends to x + 2^e y modulo 2^(e+1) exactly when J y = -F(x) / 2^e
+    (mod 2), where J is the Jacobian of F at the GF(2) scheme (the same
+    matrix at every step).  Each step takes the solution with the free
+    variables zero, entries outside the GF(2) support chosen free first, so
+    the lift stays as close to the support as the equations allow.  After
+    `bits` steps the balanced residues are taken as integers; they are
+    returned when every one is at most `bound` in magnitude and the exact
+    Brent check passes."""
+    R = len(scheme)
+    sizes = (M * K, K * N, M * N)
+    keys = [(s, x, r) for s in range(3) for x in range(sizes[s]) for r in range(R)]
+    bit = {key: (scheme[key[2]][key[0]] >> key[1]) & 1 for key in keys}
+    order = sorted(keys, key=lambda key: bit[key])  # off-support first: low columns, free if possible
+    col = {key: c for c, key in enumerate(order)}
+    eqs = [(i, j, k) for i in range(sizes[0]) for j in range(sizes[1]) for k in range(sizes[2])]
+    rows = []
+    for (i, j, k) in eqs:
+        mask = 0
+        for r in range(R):
+            u, v, w = bit[(0, i, r)], bit[(1, j, r)], bit[(2, k, r)]
+            if v & w:
+                mask ^= 1 << col[(0, i, r)]
+            if u & w:
+                mask ^= 1 << col[(1, j, r)]
+            if u & v:
+                mask ^= 1 << col[(2, k, r)]
+        rows.append(mask)
+    # Gauss-Jordan once, recording which equations each pivot row sums, so
+    # that every step only needs parities of the new right-hand side
+    piv = {}
+    zero_rows = []
+    for e, mask in enumerate(rows):
+        comb = 1 << e
+        for c, (pm, pc) in piv.items():
+            if (mask >> c) & 1:
+                mask ^= pm
+                comb ^= pc
+        if mask == 0:
+            zero_rows.append(comb)
+            continue
+        top = mask.bit_length() - 1
+        for c in list(piv):
+            pm, pc = piv[c]
+            if (pm >> top) & 1:
+                piv[c] = (pm ^ mask, pc ^ comb)
+        piv[top] = (mask, comb)
+    X = [[[bit[(s, x, r)] for r in range(R)] for x in range(sizes[s])] for s in range(3)]
+    T = [tensor_entry(M, K, N, i, j, k) for (i, j, k) in eqs]
+    mod = 2
+    for _ in range(1, bits):
+        rhs = 0
+        for e, ((i, j, k), t) in enumerate(zip(eqs, T)):
+            a, b, c = X[0][i], X[1][j], X[2][k]
+            f = sum(a[r] * b[r] * c[r] for r in range(R)) - t
+            if (f // mod) & 1:
+                rhs |= 1 << e
+        if any(bin(z & rhs).count("1") & 1 for z in zero_rows):
+            return None
+        for c, (pm, pc) in piv.items():
+            if bin(pc & rhs).count("1") & 1:
+                s, x, r = order[c]
+                X[s][x][r] += mod
+        mod *= 2
+        for Xs in X:
+            for row in Xs:
+                for r in range(R):
+                    v = row[r] % mod
+                    row[r] = v - mod if v >= mod // 2 else v
+    if max(abs(v) for Xs in X for row in Xs for v in row) > bound:
+        return None
+    U, V, W = X
+    return (U, V, W) if brent_exact(M, K, N, U, V, W) else None
+
+
 def nnz(U, V, W):
     return sum(1 for X in (U, V, W) for row in X for x in row if x)
 
@@ -193,7 +272,8 @@ def canonical(U, V, W):
             [[row[r] for r in cols] for row in W])
 
 
-def search(M, K, N, R, seeds, count=4, flips=10 ** 10, plateau=50000, over="z", log=sys.stderr):
+def search(M, K, N, R, seeds, count=4, flips=10 ** 10, plateau=50000, over="z", log=sys.stderr,
+           lift_mode="sign"):
     exe = build_walker()
     best = None
     for seed in seeds:
@@ -203,6 +283,8 @@ def search(M, K, N, R, seeds, count=4, flips=10 ** 10, plateau=50000, over="z", 
                 U, V, W = scheme
             else:
                 lifted = lift(M, K, N, scheme, rng)
+                if lifted is None and lift_mode == "2adic":
+                    lifted = lift_2adic(M, K, N, scheme)
                 if lifted is None:
                     print(f"seed {seed}: a rank-{len(scheme)} scheme did not lift", file=log)
                     continue
@@ -248,10 +330,12 @@ def main():
     ap.add_argument("--flips", type=int, default=10 ** 10, help="flip budget per seed")
     ap.add_argument("--plateau", type=int, default=50000, help="flips without a reduction before a plus step")
     ap.add_argument("--over", choices=("z", "gf2"), default="z", help="walk over the integers or GF(2)")
+    ap.add_argument("--lift", choices=("sign", "2adic"), default="sign",
+                    help="GF(2) schemes: signs on the support only, or also the 2-adic lift of every entry")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     best = search(args.M, args.K, args.N, args.R, _seeds(args.seeds), args.count, args.flips, args.plateau,
-                  args.over)
+                  args.over, lift_mode=args.lift)
     if best is None:
         print("no scheme of that rank was found and lifted", file=sys.stderr)
         return 1
@@ -259,9 +343,11 @@ def main():
     name = f"fmm_{args.M}{args.K}{args.N}_{args.R}"
     cmd = (f"python paper_1409_2908_amd/algorithms/search.py {args.M} {args.K} {args.N} {args.R} "
            f"--seeds {args.seeds} --count {args.count} --flips {args.flips} --plateau {args.plateau} "
-           f"--over {args.over}")
+           f"--over {args.over}" + (" --lift 2adic" if args.lift == "2adic" else ""))
     how = ("over the integers with coefficients in {-1,0,1}" if args.over == "z" else
-           "over GF(2), lifted to coefficients in {-1,0,1} (Brent equations mod 4 as a GF(2) linear system)")
+           "over GF(2), lifted to coefficients in {-1,0,1} (Brent equations mod 4 as a GF(2) linear system)"
+           if args.lift == "sign" else
+           "over GF(2), lifted to integers (signs on the support first, else a 2-adic lift of every entry)")
     header = [f"<{args.M},{args.K},{args.N};{args.R}> {name}",
               "Found by a random walk on the flip graph (Kauers and Moosbauer, ISSAC 2023) from the classical",
               f"scheme, {how},",
