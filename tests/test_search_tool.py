@@ -39,6 +39,43 @@ def test_search_writes_brent_exact_strassen_rank(over, tmp_path):
     assert tensor.brent_residual(U, V, W, M, K, N) == []
 
 
+@pytest.mark.parametrize("dims", [("2", "2", "2", "7"), ("3", "2", "2", "11")])
+def test_search_2adic_lift_is_brent_exact(dims, tmp_path):
+    """GF(2) walks with the 2-adic lift enabled: whatever lift is taken, the
+    written scheme passes the oracle's own exact Brent check and names the
+    lift in its regeneration command."""
+    out = tmp_path / "t.txt"
+    subprocess.run([sys.executable, SEARCH, *dims, "--seeds", "1-2", "--count", "2", "--plateau", "2000",
+                    "--over", "gf2", "--lift", "2adic", "--out", str(out)], check=True,
+                   stdout=subprocess.PIPE, stderr=subprocess.PIPE, timeout=300)
+    text = out.read_text()
+    assert "--over gf2 --lift 2adic" in text
+    M, K, N, R, U, V, W = _parse(text)
+    assert (M, K, N, R) == tuple(int(d) for d in dims)
+    assert tensor.brent_residual(U, V, W, M, K, N) == []
+
+
+def test_2adic_lift_of_strassen_mod_2():
+    """Strassen's scheme reduced modulo 2 lifts back to an exact integer
+    scheme (the Hensel steps reach a solution over the integers)."""
+    sys.path.insert(0, ALGS)
+    import search
+    from oracle import algorithms
+    a = algorithms.get("strassen_222_7")
+    scheme = []
+    for r in range(a.R):
+        masks = [sum(((X[i][r] & 1) << i) for i in range(len(X))) for X in (a.U, a.V, a.W)]
+        scheme.append(tuple(masks))
+    lifted = search.lift_2adic(2, 2, 2, scheme)
+    assert lifted is not None
+    U, V, W = lifted
+    assert tensor.brent_residual(U, V, W, 2, 2, 2) == []
+    # same support as the GF(2) scheme, entries +-1 there
+    for X, Y in ((U, a.U), (V, a.V), (W, a.W)):
+        for row, ref in zip(X, Y):
+            assert [abs(x) for x in row] == [abs(y) for y in ref]
+
+
 def test_search_is_deterministic_per_seed(tmp_path):
     outs = []
     for i in range(2):
