@@ -243,7 +243,8 @@ _PERMUTED = {"fmm_332_15": "fmm_323_15", "fmm_233_15": "fmm_323_15",
              "fmm_442_26": "fmm_424_26", "fmm_244_26": "fmm_424_26",
              "fmm_232_11": "fmm_223_11", "fmm_322_11": "fmm_223_11",
              "fmm_252_18": "fmm_225_18", "fmm_522_18": "fmm_225_18",
-             "fmm_343_29": "fmm_334_29", "fmm_433_29": "fmm_334_29"}
+             "fmm_343_29": "fmm_334_29", "fmm_433_29": "fmm_334_29",
+             "fmm_344_38": "fmm_434_38", "fmm_443_38": "fmm_434_38"}
 
 
 def get(name) -> Algorithm:

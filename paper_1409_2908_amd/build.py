@@ -24,7 +24,11 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 
 def _compile(src, verbose):
     obj = os.path.join(BUILD, src.replace("/", "_") + ".o")
-    cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    # The addition kernels (csrc/gen/) round every multiply and add of a chain
+    # separately, as the oracle's chains do: a contracted multiply-add differs
+    # in the last bit once a coefficient or a view's scale is not 0 or +-2^e.
+    extra = ["-ffp-contract=off"] if src.startswith("gen/") else []
+    cmd = [HIPCC] + FLAGS + extra + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)

@@ -512,6 +512,19 @@ constexpr WTable<ID> make_w_table() {
 template <int ID>
 __constant__ WTable<ID> kWTable = make_w_table<ID>();
 
+// Whether every W coefficient of a base case is 0 or +-2^e: then c * y is
+// exact and a fused multiply-add rounds like the scaled add of the one-level
+// chains, so the fused combination kernels below keep their bits.
+template <int ID>
+constexpr bool w_pow2() {
+  for (int k = 0; k < Comb<ID>::MN; ++k)
+    for (int r = 0; r < Comb<ID>::R; ++r) {
+      const int c = Comb<ID>::coef(k, r) < 0 ? -Comb<ID>::coef(k, r) : Comb<ID>::coef(k, r);
+      if (c != 0 && (c & (c - 1)) != 0) return false;
+    }
+  return true;
+}
+
 // W-combination, two levels fused, for narrow base cases (R <= 8) with FP32
 // products and FP32 outputs whose pairs of adjacent positions are all 8-byte
 // aligned (the host sets CombineArgs::pairs), in registers: each thread owns
@@ -524,6 +537,7 @@ __constant__ WTable<ID> kWTable = make_w_table<ID>();
 // wavefronts per SIMD).
 template <int ID>
 __global__ void __launch_bounds__(kAddTX * kAddTY) combine2p_kernel(CombineArgs a) {
+  static_assert(w_pow2<ID>(), "fused combination needs W coefficients 0 or +-2^e");
   using CB = Comb<ID>;
   constexpr int R = CB::R, MN = CB::MN, N = Alg<ID>::N, M = Alg<ID>::M;
   const int64_t q = ((int64_t)blockIdx.x * kAddTX + threadIdx.x) * 2;
@@ -604,6 +618,7 @@ __global__ void __launch_bounds__(kAddTX * kAddTY) combine2p_kernel(CombineArgs 
 // one-level passes, so the results are bitwise theirs.
 template <int ID>
 __global__ void __launch_bounds__(256) combine2_kernel(CombineArgs a) {
+  static_assert(w_pow2<ID>(), "fused combination needs W coefficients 0 or +-2^e");
   using CB = Comb<ID>;
   constexpr int R = CB::R, MN = CB::MN, N = Alg<ID>::N, M = Alg<ID>::M;
   constexpr int RC = 4, CPW = (MN + 3) / 4;

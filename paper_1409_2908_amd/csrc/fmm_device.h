@@ -53,6 +53,10 @@ struct Comb {
 // exact power-of-two scaling), later terms add; each operation rounds once.
 template <int C, bool FIRST>
 __device__ __forceinline__ void chain_term(double& acc, double x) {
+  // c * x and the add round separately, also for |c| = 3 (where a contracted
+  // multiply-add would round once and differ in the last bit); for c = +-2^e
+  // the product is exact and both forms agree
+#pragma clang fp contract(off)
   if constexpr (FIRST) {
     if constexpr (C == 1) acc = x;
     else if constexpr (C == -1) acc = -x;

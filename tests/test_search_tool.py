@@ -89,7 +89,7 @@ def test_search_is_deterministic_per_seed(tmp_path):
     assert R == 11 and tensor.brent_residual(U, V, W, M, K, N) == []
 
 
-@pytest.mark.parametrize("name", ["fmm_323_15", "fmm_423_20", "fmm_424_26", "fmm_334_29"])
+@pytest.mark.parametrize("name", ["fmm_323_15", "fmm_423_20", "fmm_424_26", "fmm_334_29", "fmm_434_38"])
 def test_shipped_searched_tables_name_their_command(name):
     text = open(os.path.join(ALGS, name + ".txt")).read()
     m = re.search(r"Regenerate: python paper_1409_2908_amd/algorithms/search.py (\d) (\d) (\d) (\d+) ", text)
